@@ -1,0 +1,202 @@
+/*
+ * bigmeans.h -- C ABI of the Big-means library for one AMD Instinct MI355X.
+ *
+ * Big-means (Mussabayev, Mladenovic, Mussabayev, Jarboui, "How to Use K-means
+ * for Big Data Clustering?", Alg. 1 and Sec. 3) clusters n points in d
+ * dimensions into k clusters by repeatedly drawing a uniform sample of s
+ * points, reseeding the degenerate (empty) centroids of the best solution so
+ * far with K-means++, running K-means (Lloyd) on the sample from there, and
+ * keeping the result when its sample objective is lower.  A final pass assigns
+ * every point to its nearest centroid and returns the objective of Eq. (1),
+ * the sum of squared distances of points to their nearest centroids.
+ *
+ * Naming: n = number of points, d = number of features (the paper's m and n).
+ *
+ * Conventions shared by every entry point
+ *   - All functions return a bm_status; BM_OK (0) on success, a negative code
+ *     otherwise, with a message available from bm_last_error() (per thread).
+ *     No exception or abort crosses this boundary.
+ *   - Buffers named "device" are device pointers on the current HIP device
+ *     (for example torch tensors' data_ptr()); "host" buffers are ordinary
+ *     host memory.  The caller owns every buffer it passes.  The library owns
+ *     only an internal scratch pool, kept between calls and released by
+ *     bm_release_scratch().
+ *   - Arrays are row-major: X is n x d, centroids are k x d FP32.  A degenerate
+ *     centroid (Sec. 3.3: an empty cluster, or one never initialised) is
+ *     reported with degenerate[j] = 1 and NaN coordinates, and receives no
+ *     points.
+ *   - Calls are synchronous with respect to the host: they enqueue on
+ *     opt->stream (NULL = the null stream) and return when the results are
+ *     ready.  Calls from several host threads must use distinct streams and
+ *     are serialised on the scratch pool.
+ *   - Random numbers come from the counter-based stream documented in
+ *     bm_rng.h (Philox4x32-10 keyed by seed); the same (seed, sample index)
+ *     always yields the same sample and the same K-means++ draws.
+ */
+#ifndef BIGMEANS_H
+#define BIGMEANS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bm_status;
+
+enum {
+  BM_OK = 0,
+  BM_EINVAL = -1,      /* invalid argument (sizes, null pointers, options) */
+  BM_ENOMEM = -2,      /* device or host allocation failed                 */
+  BM_EDEVICE = -3,     /* a HIP call or a kernel failed                    */
+  BM_ENOTSUP = -4,     /* a valid request this build cannot serve          */
+  BM_ECANCELLED = -5   /* the work was cancelled                           */
+};
+
+enum { BM_F32 = 0, BM_BF16 = 1 };               /* element type of X       */
+enum { BM_STOP_SHIFT = 0, BM_STOP_REL_OBJ = 1 }; /* Lloyd stop rule         */
+enum { BM_CMP_FOPT = 0, BM_CMP_RESAMPLE = 1 };   /* keep-the-best reference */
+enum { BM_PREC_FP32 = 0 };                       /* distance arithmetic     */
+
+#define BM_ABI_VERSION 1
+
+/* Options.  Fill with bm_default_options(); fields are read only when
+ * struct_size covers them, so callers built against an older header keep
+ * working. */
+typedef struct bm_options {
+  uint32_t struct_size;   /* sizeof(bm_options)                                   */
+  int32_t x_dtype;        /* BM_F32 (default) or BM_BF16 (uint16 bit patterns)    */
+  int32_t max_iter;       /* Lloyd assign+update rounds per sample (default 100)  */
+  double tol;             /* stop tolerance (default 1e-4)                        */
+  int32_t stop_rule;      /* BM_STOP_SHIFT: stop when no centroid moves by tol    */
+                          /* or more; BM_STOP_REL_OBJ: stop when the relative     */
+                          /* decrease of the objective is <= tol (Sec. 5 rule)    */
+  int32_t n_local_trials; /* K-means++ candidates per new centre (default 3,      */
+                          /* Sec. 5); 1 is plain D^2 sampling                     */
+  int32_t compare_rule;   /* BM_CMP_FOPT: replace the incumbent when f(C'',P) <   */
+                          /* f_opt (Alg. 1); BM_CMP_RESAMPLE: when f(C'',P) <     */
+                          /* f(C,P) of the incumbent on the new sample (Sec. 3.2) */
+  int32_t precision;      /* BM_PREC_FP32                                         */
+  void* stream;           /* hipStream_t to run on; NULL = null stream            */
+  int32_t grid;           /* workgroups of the cooperative solver; 0 = automatic  */
+  int32_t t_start;        /* index of the first sample (resume); default 0        */
+  int32_t resume;         /* 1: centroids (device), degenerate (host) and         */
+                          /* f_opt_in carry an incumbent into bigmeans_fit        */
+  double f_opt_in;        /* incumbent objective when resume = 1                  */
+  uint32_t spin_limit;    /* bound on a grid-barrier wait, in polls; 0 = default; */
+                          /* a wait that exceeds it aborts the call (BM_EDEVICE)  */
+  int32_t* sample_idx;    /* optional device out, n_samples x s sampled indices   */
+  double* sample_f;       /* optional host out, n_samples objectives f(C'',P)     */
+} bm_options;
+
+/* Per-call counters (all optional; pass NULL). */
+typedef struct bm_stats {
+  uint32_t struct_size;   /* sizeof(bm_stats)                                     */
+  int32_t samples;        /* samples processed                                    */
+  int32_t replacements;   /* incumbent replacements (keep-the-best)               */
+  int32_t grid;           /* workgroups the solver ran with                       */
+  int64_t lloyd_iters;    /* assignment passes over samples inside K-means        */
+  int64_t reseeded;       /* centroids placed by K-means++                        */
+  int64_t n_d;            /* distance evaluations at sample level (Sec. 5's n_d)  */
+  int64_t boundary_draws; /* D^2 draws that fell within 1e-12 W of a boundary of  */
+                          /* the running sum (rounding-order sensitive)           */
+  double f_opt;           /* objective of the incumbent on its own sample         */
+  double ms_solver;       /* device time of the sample loop                       */
+  double ms_final;        /* device time of the final assignment pass             */
+} bm_stats;
+
+/* Fill *opt with defaults (struct_size set).  Returns BM_EINVAL on NULL. */
+bm_status bm_default_options(bm_options* opt);
+
+/* Message of the last failure on this thread ("" if none).  Owned by the
+ * library, valid until the next call on this thread. */
+const char* bm_last_error(void);
+
+/* Release the library's device scratch pool (it is re-created on demand). */
+bm_status bm_release_scratch(void);
+
+/* BM_ABI_VERSION of the built library. */
+int32_t bm_abi_version(void);
+
+/*
+ * bigmeans_fit -- Big-means, Alg. 1, followed by the final assignment of
+ * Sec. 3.4.
+ *   X           device, n x d, FP32 (or BF16 bit patterns when opt->x_dtype is
+ *               BM_BF16); read only.
+ *   n, d, k, s  1 <= k <= s <= n, d >= 1, n < 2^31.
+ *   n_samples   number of samples processed (the stop condition; >= 1).
+ *   seed        key of the random stream.
+ *   opt         options, or NULL for defaults.
+ *   centroids   device, k x d FP32, out (in/out when opt->resume = 1).
+ *               Degenerate rows are NaN.
+ *   sse         host, out: objective of Eq. (1) on all of X, summed in FP64;
+ *               may be NULL to skip the final pass together with labels.
+ *   labels      device, n int32, out: nearest non-degenerate centroid of every
+ *               point (exact ties to the lowest index); may be NULL.
+ *   degenerate  host, k bytes, out (in/out when resuming); may be NULL unless
+ *               resuming.
+ *   stats       host, out; may be NULL.
+ * Errors: BM_EINVAL for bad sizes/pointers/options, BM_ENOMEM when scratch
+ * cannot be allocated, BM_ENOTSUP when k x d exceeds what a workgroup can
+ * stage, BM_EDEVICE on a HIP failure or an aborted grid barrier.
+ */
+bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s,
+                       int32_t n_samples, uint64_t seed, const bm_options* opt,
+                       float* centroids, double* sse, int32_t* labels, uint8_t* degenerate,
+                       bm_stats* stats);
+
+/*
+ * kmeans_assign -- assignment step (Sec. 2) and objective, Eq. (1): every row
+ * of X goes to its nearest non-degenerate centroid (exact ties to the lowest
+ * index), distances in FP32 by direct differences, the sum in FP64.
+ *   X        device n x d (FP32 or BF16 per opt->x_dtype).
+ *   C        device k x d FP32.
+ *   deg      host k bytes (1 = skip this centroid) or NULL (all active).
+ *   labels   device n int32 out, or NULL.
+ *   min_d2   device n FP32 out (squared distance to the chosen centroid), or NULL.
+ *   sse      host FP64 out, or NULL.
+ * At least one centroid must be active.
+ */
+bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, const uint8_t* deg,
+                        int32_t k, const bm_options* opt, int32_t* labels, float* min_d2,
+                        double* sse);
+
+/*
+ * kmeanspp_seed -- K-means++ (Sec. 2, greedy form of Sec. 5) applied to the
+ * degenerate slots of C, as in the reseeding step of Alg. 1 (Sec. 3.3).
+ *   P          device s x d FP32: the points to seed from (a sample).
+ *   C          device k x d FP32, in/out: slots with deg[j] = 0 are kept.
+ *   deg        host k bytes, in/out: 1 = fill this slot.  Slots are filled in
+ *              ascending order; if every remaining D^2 is zero they stay 1.
+ *   seed, stream_id  the draws use sample index t = stream_id (< 2^32).
+ *   opt        n_local_trials (1..8) is read from here.
+ */
+bm_status kmeanspp_seed(const float* P, int64_t s, int32_t d, int32_t k, float* C, uint8_t* deg,
+                        uint64_t seed, uint64_t stream_id, const bm_options* opt);
+
+/*
+ * kmeans_lloyd -- K-means local search (Sec. 2) on the rows of P from C, with
+ * the stop rule, tolerance and iteration cap of opt; a centroid whose cluster
+ * empties becomes degenerate (Sec. 3.3).
+ *   P        device s x d FP32.
+ *   C        device k x d FP32, in/out.      deg  host k bytes, in/out.
+ *   labels   device s int32 out (assignment to the returned C), or NULL.
+ *   f        host out: objective of the returned C on P (FP64), or NULL.
+ *   passes   host out: assignment passes run, or NULL.
+ */
+bm_status kmeans_lloyd(const float* P, int64_t s, int32_t d, int32_t k, float* C, uint8_t* deg,
+                       const bm_options* opt, int32_t* labels, double* f, int32_t* passes);
+
+/*
+ * bm_sample_indices -- the uniform sample of s distinct indices out of n that
+ * bigmeans_fit uses for sample index t (Sec. 3.1, 3.5): the s points with the
+ * smallest (key, index) pairs, in ascending index order.
+ *   idx   device s int32 out.
+ */
+bm_status bm_sample_indices(int64_t n, int64_t s, uint64_t seed, int32_t t, int32_t* idx,
+                            const bm_options* opt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BIGMEANS_H */

@@ -1,0 +1,230 @@
+"""Thin ctypes binding over libbigmeans.so (the C ABI in include/bigmeans.h).
+
+Argument marshalling only: torch tensors supply device memory and the HIP
+stream; every step of the computation runs in the library's HIP kernels.  The
+library must have been built (``python -m paper_2204_07485_amd.build``); a
+missing library is an error, there is no fallback.
+"""
+import ctypes as ct
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbigmeans.so")
+
+BM_OK, BM_EINVAL, BM_ENOMEM, BM_EDEVICE, BM_ENOTSUP, BM_ECANCELLED = 0, -1, -2, -3, -4, -5
+BM_F32, BM_BF16 = 0, 1
+BM_STOP_SHIFT, BM_STOP_REL_OBJ = 0, 1
+BM_CMP_FOPT, BM_CMP_RESAMPLE = 0, 1
+BM_PREC_FP32 = 0
+
+FUNCTIONS = ["bm_default_options", "bm_last_error", "bm_release_scratch", "bm_abi_version",
+             "bigmeans_fit", "kmeans_assign", "kmeanspp_seed", "kmeans_lloyd",
+             "bm_sample_indices"]
+
+
+class BigmeansError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bigmeans error {code}: {msg}")
+        self.code = code
+
+
+class Options(ct.Structure):
+    _fields_ = [("struct_size", ct.c_uint32), ("x_dtype", ct.c_int32),
+                ("max_iter", ct.c_int32), ("tol", ct.c_double),
+                ("stop_rule", ct.c_int32), ("n_local_trials", ct.c_int32),
+                ("compare_rule", ct.c_int32), ("precision", ct.c_int32),
+                ("stream", ct.c_void_p), ("grid", ct.c_int32), ("t_start", ct.c_int32),
+                ("resume", ct.c_int32), ("f_opt_in", ct.c_double),
+                ("spin_limit", ct.c_uint32), ("sample_idx", ct.c_void_p),
+                ("sample_f", ct.c_void_p)]
+
+
+class Stats(ct.Structure):
+    _fields_ = [("struct_size", ct.c_uint32), ("samples", ct.c_int32),
+                ("replacements", ct.c_int32), ("grid", ct.c_int32),
+                ("lloyd_iters", ct.c_int64), ("reseeded", ct.c_int64), ("n_d", ct.c_int64),
+                ("boundary_draws", ct.c_int64), ("f_opt", ct.c_double),
+                ("ms_solver", ct.c_double), ("ms_final", ct.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}
+
+
+_LIB = None
+
+
+def load(path=LIB_PATH):
+    """Load libbigmeans.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_2204_07485_amd.build` (no CPU fallback exists)")
+    L = ct.CDLL(path)
+    P, I32, I64, U64 = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_uint64
+    L.bm_default_options.argtypes = [P]
+    L.bm_default_options.restype = I32
+    L.bm_last_error.argtypes = []
+    L.bm_last_error.restype = ct.c_char_p
+    L.bm_release_scratch.argtypes = []
+    L.bm_release_scratch.restype = I32
+    L.bm_abi_version.argtypes = []
+    L.bm_abi_version.restype = I32
+    L.bigmeans_fit.argtypes = [P, I64, I32, I32, I64, I32, U64, P, P, P, P, P, P]
+    L.bigmeans_fit.restype = I32
+    L.kmeans_assign.argtypes = [P, I64, I32, P, P, I32, P, P, P, P]
+    L.kmeans_assign.restype = I32
+    L.kmeanspp_seed.argtypes = [P, I64, I32, I32, P, P, U64, U64, P]
+    L.kmeanspp_seed.restype = I32
+    L.kmeans_lloyd.argtypes = [P, I64, I32, I32, P, P, P, P, P, P]
+    L.kmeans_lloyd.restype = I32
+    L.bm_sample_indices.argtypes = [I64, I64, U64, I32, P, P]
+    L.bm_sample_indices.restype = I32
+    _LIB = L
+    return L
+
+
+def _check(rc):
+    if rc != BM_OK:
+        msg = _LIB.bm_last_error().decode(errors="replace")
+        raise BigmeansError(rc, msg)
+
+
+def options(stream=None, **kw):
+    """bm_options with defaults, overridden by keyword fields."""
+    L = load()
+    o = Options()
+    _check(L.bm_default_options(ct.byref(o)))
+    if stream is None and torch.cuda.is_available():
+        stream = torch.cuda.current_stream().cuda_stream
+    o.stream = stream
+    for key, val in kw.items():
+        if not hasattr(o, key):
+            raise TypeError(f"unknown option {key}")
+        setattr(o, key, val)
+    return o
+
+
+def _dev_ptr(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ct.c_void_p(t.data_ptr())
+
+
+def _x_ptr(X):
+    if X.dtype == torch.float32:
+        return _dev_ptr(X, torch.float32, "X"), BM_F32
+    if X.dtype in (torch.uint16, torch.int16, torch.bfloat16):
+        return ct.c_void_p(X.data_ptr()), BM_BF16
+    raise TypeError("X must be float32, or bfloat16 / 16-bit BF16 bit patterns")
+
+
+def bigmeans_fit(X, k, s, n_samples, seed, want_labels=True, want_sse=True, state=None,
+                 sample_idx=False, sample_f=True, **opts):
+    """Big-means on X (device tensor n x d).
+
+    state: optional (centroids tensor, degenerate uint8 array, f_opt) to resume from.
+    Returns a dict: centroids (k x d float32 tensor, NaN rows degenerate),
+    degenerate (numpy uint8), sse, labels (int32 tensor or None), f_opt,
+    sample_f (numpy), sample_idx (int32 tensor or None), stats.
+    """
+    L = load()
+    n, d = X.shape
+    xp, xdt = _x_ptr(X)
+    o = options(x_dtype=xdt, **opts)
+    cent = torch.empty((k, d), dtype=torch.float32, device=X.device)
+    deg = np.ones(k, dtype=np.uint8)
+    if state is not None:
+        cent.copy_(state[0])
+        deg[:] = np.asarray(state[1], dtype=np.uint8)
+        o.resume = 1
+        o.f_opt_in = float(state[2])
+    labels = torch.empty(n, dtype=torch.int32, device=X.device) if want_labels else None
+    sidx = torch.empty((n_samples, s), dtype=torch.int32, device=X.device) if sample_idx else None
+    sf = np.zeros(n_samples, dtype=np.float64)
+    if sidx is not None:
+        o.sample_idx = sidx.data_ptr()
+    if sample_f:
+        o.sample_f = sf.ctypes.data
+    sse = ct.c_double(0.0)
+    st = Stats()
+    st.struct_size = ct.sizeof(Stats)
+    rc = L.bigmeans_fit(xp, n, d, k, s, n_samples, ct.c_uint64(seed), ct.byref(o),
+                        ct.c_void_p(cent.data_ptr()),
+                        ct.byref(sse) if want_sse else None,
+                        ct.c_void_p(labels.data_ptr()) if labels is not None else None,
+                        deg.ctypes.data_as(ct.c_void_p), ct.byref(st))
+    _check(rc)
+    return {"centroids": cent, "degenerate": deg, "sse": sse.value if want_sse else None,
+            "labels": labels, "f_opt": st.f_opt, "sample_f": sf, "sample_idx": sidx,
+            "stats": st.as_dict()}
+
+
+def kmeans_assign(X, C, deg=None, want_labels=True, want_min_d2=False, **opts):
+    L = load()
+    n, d = X.shape
+    k = C.shape[0]
+    xp, xdt = _x_ptr(X)
+    o = options(x_dtype=xdt, **opts)
+    cp = _dev_ptr(C, torch.float32, "C")
+    dg = None if deg is None else np.ascontiguousarray(deg, dtype=np.uint8)
+    labels = torch.empty(n, dtype=torch.int32, device=X.device) if want_labels else None
+    mind = torch.empty(n, dtype=torch.float32, device=X.device) if want_min_d2 else None
+    sse = ct.c_double(0.0)
+    rc = L.kmeans_assign(xp, n, d, cp, None if dg is None else dg.ctypes.data_as(ct.c_void_p), k,
+                         ct.byref(o), None if labels is None else ct.c_void_p(labels.data_ptr()),
+                         None if mind is None else ct.c_void_p(mind.data_ptr()), ct.byref(sse))
+    _check(rc)
+    return labels, mind, sse.value
+
+
+def kmeanspp_seed(P, C, deg, seed, stream_id, n_local_trials=3, **opts):
+    """Reseed the slots of C (in place) with deg[j] = 1; returns the new flags."""
+    L = load()
+    s, d = P.shape
+    k = C.shape[0]
+    o = options(n_local_trials=n_local_trials, **opts)
+    dg = np.array(deg, dtype=np.uint8, copy=True)
+    rc = L.kmeanspp_seed(_dev_ptr(P, torch.float32, "P"), s, d, k, _dev_ptr(C, torch.float32, "C"),
+                         dg.ctypes.data_as(ct.c_void_p), ct.c_uint64(seed),
+                         ct.c_uint64(stream_id), ct.byref(o))
+    _check(rc)
+    return dg
+
+
+def kmeans_lloyd(P, C, deg, **opts):
+    """Lloyd on P from C (updated in place); returns (deg, labels, f, passes)."""
+    L = load()
+    s, d = P.shape
+    k = C.shape[0]
+    o = options(**opts)
+    dg = np.array(deg, dtype=np.uint8, copy=True)
+    labels = torch.empty(s, dtype=torch.int32, device=P.device)
+    f = ct.c_double(0.0)
+    passes = ct.c_int32(0)
+    rc = L.kmeans_lloyd(_dev_ptr(P, torch.float32, "P"), s, d, k, _dev_ptr(C, torch.float32, "C"),
+                        dg.ctypes.data_as(ct.c_void_p), ct.byref(o),
+                        ct.c_void_p(labels.data_ptr()), ct.byref(f), ct.byref(passes))
+    _check(rc)
+    return dg, labels, f.value, passes.value
+
+
+def sample_indices(n, s, seed, t, device="cuda", **opts):
+    L = load()
+    idx = torch.empty(s, dtype=torch.int32, device=device)
+    o = options(**opts)
+    rc = L.bm_sample_indices(n, s, ct.c_uint64(seed), t, ct.c_void_p(idx.data_ptr()), ct.byref(o))
+    _check(rc)
+    return idx
+
+
+def release_scratch():
+    _check(load().bm_release_scratch())

@@ -1,0 +1,587 @@
+// bm_api.hip -- the C ABI (include/bigmeans.h): argument checks, option
+// defaults, the device scratch pool, launches and error mapping.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "bm_internal.h"
+
+namespace bm {
+
+// ---------------------------------------------------------------------------
+// errors
+
+static thread_local char g_err[512] = "";
+
+bm_status set_error(bm_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+#define BM_HIP(call)                                                                      \
+  do {                                                                                    \
+    const hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                                 \
+      return set_error(BM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));        \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// scratch pool: one growing device allocation per device, guarded by a mutex
+
+static std::mutex g_mu;
+struct Pool {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+static Pool g_pool[64];
+
+void* scratch_get(size_t bytes, hipStream_t stream, bm_status* st) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    *st = set_error(BM_EDEVICE, "no current HIP device");
+    return nullptr;
+  }
+  Pool& p = g_pool[dev];
+  if (p.bytes >= bytes) {
+    *st = BM_OK;
+    return p.ptr;
+  }
+  if (p.ptr) {
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(p.ptr);
+    p.ptr = nullptr;
+    p.bytes = 0;
+  }
+  size_t want = bytes + bytes / 4 + (1u << 20);
+  if (hipMalloc(&p.ptr, want) != hipSuccess) {
+    (void)hipGetLastError();
+    p.ptr = nullptr;
+    *st = set_error(BM_ENOMEM, "cannot allocate %zu bytes of device scratch", want);
+    return nullptr;
+  }
+  p.bytes = want;
+  *st = BM_OK;
+  return p.ptr;
+}
+
+void scratch_release() {
+  for (auto& p : g_pool) {
+    if (p.ptr) (void)hipFree(p.ptr);
+    p.ptr = nullptr;
+    p.bytes = 0;
+  }
+}
+
+// Bump layout over the scratch block: first pass sizes, second pass binds.
+struct Layout {
+  size_t off = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * (count ? count : 1);
+    return p;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// options
+
+static void defaults(bm_options* o) {
+  memset(o, 0, sizeof *o);
+  o->struct_size = sizeof(bm_options);
+  o->x_dtype = BM_F32;
+  o->max_iter = 100;
+  o->tol = 1e-4;
+  o->stop_rule = BM_STOP_SHIFT;
+  o->n_local_trials = 3;
+  o->compare_rule = BM_CMP_FOPT;
+  o->precision = BM_PREC_FP32;
+}
+
+static bm_status resolve(const bm_options* in, bm_options* out) {
+  defaults(out);
+  if (in) {
+    if (in->struct_size < sizeof(uint32_t) || in->struct_size > sizeof(bm_options))
+      return set_error(BM_EINVAL, "bm_options.struct_size %u not recognised", in->struct_size);
+    memcpy(out, in, in->struct_size);
+    out->struct_size = sizeof(bm_options);
+  }
+  if (out->x_dtype != BM_F32 && out->x_dtype != BM_BF16)
+    return set_error(BM_EINVAL, "x_dtype %d", out->x_dtype);
+  if (out->max_iter < 1) return set_error(BM_EINVAL, "max_iter must be >= 1");
+  if (!(out->tol >= 0.0)) return set_error(BM_EINVAL, "tol must be >= 0");
+  if (out->stop_rule != BM_STOP_SHIFT && out->stop_rule != BM_STOP_REL_OBJ)
+    return set_error(BM_EINVAL, "stop_rule %d", out->stop_rule);
+  if (out->n_local_trials < 1 || out->n_local_trials > kMaxTrials)
+    return set_error(BM_EINVAL, "n_local_trials must be in [1, %d]", kMaxTrials);
+  if (out->compare_rule != BM_CMP_FOPT && out->compare_rule != BM_CMP_RESAMPLE)
+    return set_error(BM_EINVAL, "compare_rule %d", out->compare_rule);
+  if (out->precision != BM_PREC_FP32) return set_error(BM_ENOTSUP, "precision %d", out->precision);
+  if (out->grid < 0 || out->grid > kMaxGrid) return set_error(BM_EINVAL, "grid %d", out->grid);
+  if (out->t_start < 0) return set_error(BM_EINVAL, "t_start must be >= 0");
+  return BM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solver configuration shared by the entry points that run the solver
+
+struct SolverPlan {
+  int dm = 0;
+  int grid = 0;
+  int cand_cap = 0;
+  bool sums_in_lds = false;
+  size_t lds = 0;
+};
+
+static bm_status plan_solver(int d, int k, int64_t s, int64_t n_points, int grid_req,
+                             SolverPlan* sp) {
+  sp->dm = padded_dim(d);
+  if (sp->dm < 0) return set_error(BM_ENOTSUP, "d = %d exceeds the limit of 256", d);
+  size_t lds_max = 0;
+  bm_status st = max_lds_per_block(&lds_max);
+  if (st != BM_OK) return st;
+  const size_t budget = lds_max > 2048 ? lds_max - 2048 : lds_max;  // static LDS of the kernel
+  bool found = false;
+  for (int cap = 4096; cap >= 256 && !found; cap >>= 1) {
+    for (int sl = 1; sl >= 0 && !found; --sl) {
+      const size_t need = solver_lds_bytes(sp->dm, k, d, 0, cap, sl != 0);
+      if (need <= budget) {
+        sp->cand_cap = cap;
+        sp->sums_in_lds = sl != 0;
+        sp->lds = need;
+        found = true;
+      }
+    }
+  }
+  if (!found)
+    return set_error(BM_ENOTSUP, "k*d = %d*%d centroids do not fit in one workgroup's LDS", k, d);
+  int gmax = 0;
+  st = solver_max_grid(sp->dm, sp->lds, &gmax);
+  if (st != BM_OK) return st;
+  int g = grid_req;
+  if (g <= 0) {
+    const int64_t want = (s + 511) / 512;
+    g = static_cast<int>(want < 1 ? 1 : (want > gmax ? gmax : want));
+  }
+  if (g > gmax) g = gmax;
+  const int64_t pairs = (n_points + 1) / 2;
+  if (g > s) g = static_cast<int>(s);
+  if (g > pairs) g = static_cast<int>(pairs);
+  if (g < 1) g = 1;
+  sp->grid = g;
+  return BM_OK;
+}
+
+struct SolverBuffers {
+  SolverArgs a;
+  double* partial = nullptr;      // final assignment pass: per-workgroup objective
+  unsigned int* done = nullptr;   //   arrival counter of its last-workgroup reduction
+  double* sse_dev = nullptr;      //   the objective
+  size_t bytes = 0;
+  size_t ctrl_bytes = 0;  // prefix cleared before each launch
+};
+
+// Lay out every solver buffer; with base == nullptr only the size is computed.
+static void layout_solver(char* base, int64_t s, int d, int k, int T, int cand_cap, bool own_P,
+                          bool own_idx, bool own_labels, bool own_inc, int final_grid,
+                          SolverBuffers* b) {
+  Layout L;
+  L.base = base;
+  SolverArgs& a = b->a;
+  a.bar = L.take<GridBarrier>(1);
+  a.err = L.take<int32_t>(1);
+  a.counters = L.take<int64_t>(kNumCounters);
+  a.cand_count = L.take<uint32_t>(1);
+  a.hist = L.take<uint32_t>(3 * 256);
+  a.sums = L.take<double>(3 * static_cast<size_t>(k) * d);
+  a.cnt = L.take<int32_t>(3 * static_cast<size_t>(k));
+  b->ctrl_bytes = L.off;
+  a.c64 = L.take<double>(2 * static_cast<size_t>(k) * d);
+  a.thr = L.take<uint64_t>(2);
+  a.sse_part = L.take<double>(2 * kMaxGrid);
+  a.wsum = L.take<double>(kMaxGrid);
+  a.phi_part = L.take<double>(static_cast<size_t>(kMaxGrid) * kMaxTrials);
+  a.cand = L.take<int64_t>(kMaxTrials);
+  a.wg_lo = L.take<uint32_t>(kMaxGrid);
+  a.wg_off = L.take<uint32_t>(kMaxGrid);
+  a.cand_key = L.take<uint64_t>(cand_cap);
+  a.cand_idx = L.take<int32_t>(cand_cap);
+  a.w = L.take<double>(s);
+  a.sample_f = L.take<double>(T > 0 ? T : 1);
+  float* P = L.take<float>(own_P ? static_cast<size_t>(s) * d : 1);
+  int32_t* idx = L.take<int32_t>(own_idx ? s : 1);
+  int32_t* lab = L.take<int32_t>(own_labels ? s : 1);
+  float* Cinc = L.take<float>(own_inc ? static_cast<size_t>(k) * d : 1);
+  uint8_t* deg = L.take<uint8_t>(k);
+  double* fopt = L.take<double>(1);
+  if (own_P) a.P = P;
+  if (own_idx) a.idx = idx;
+  if (own_labels) a.labels = lab;
+  if (own_inc) a.Cinc = Cinc;
+  a.deg_inc = deg;
+  a.f_opt = fopt;
+  b->partial = L.take<double>(final_grid > 0 ? final_grid : 1);
+  b->done = L.take<unsigned int>(1);
+  b->sse_dev = L.take<double>(1);
+  b->bytes = L.off + 256;
+}
+
+static bm_status prepare_solver(hipStream_t stream, int64_t s, int d, int k, int T, int cand_cap,
+                                bool own_P, bool own_idx, bool own_labels, bool own_inc,
+                                int final_grid, SolverBuffers* b) {
+  SolverArgs keep = b->a;
+  layout_solver(nullptr, s, d, k, T, cand_cap, own_P, own_idx, own_labels, own_inc, final_grid, b);
+  bm_status st = BM_OK;
+  char* base = static_cast<char*>(scratch_get(b->bytes, stream, &st));
+  if (!base) return st;
+  b->a = keep;
+  layout_solver(base, s, d, k, T, cand_cap, own_P, own_idx, own_labels, own_inc, final_grid, b);
+  BM_HIP(hipMemsetAsync(base, 0, b->ctrl_bytes, stream));
+  if (final_grid > 0) BM_HIP(hipMemsetAsync(b->done, 0, sizeof(unsigned int), stream));
+  return BM_OK;
+}
+
+static bm_status check_solver_error(const SolverArgs& a, hipStream_t stream, int32_t* code_out) {
+  int32_t code = 0;
+  BM_HIP(hipMemcpyAsync(&code, a.err, sizeof code, hipMemcpyDeviceToHost, stream));
+  BM_HIP(hipStreamSynchronize(stream));
+  if (code_out) *code_out = code;
+  switch (code) {
+    case kErrNone: return BM_OK;
+    case kErrBarrier:
+      return set_error(BM_EDEVICE, "solver aborted: a grid-barrier wait exceeded its bound");
+    case kErrSelect: return set_error(BM_EDEVICE, "solver aborted: sampler bookkeeping inconsistent");
+    case kErrSeed: return set_error(BM_EDEVICE, "solver aborted: K-means++ found no candidate");
+    default: return set_error(BM_EDEVICE, "solver aborted with code %d", code);
+  }
+}
+
+static bm_status check_sizes(int64_t n, int d, int k, int64_t s) {
+  if (n < 1 || n > 2147483647LL) return set_error(BM_EINVAL, "n = %lld out of [1, 2^31)", (long long)n);
+  if (d < 1) return set_error(BM_EINVAL, "d = %d must be >= 1", d);
+  if (k < 1) return set_error(BM_EINVAL, "k = %d must be >= 1", k);
+  if (s < k || s > n) return set_error(BM_EINVAL, "need k <= s <= n (k=%d, s=%lld, n=%lld)", k,
+                                       (long long)s, (long long)n);
+  return BM_OK;
+}
+
+static float elapsed_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+  return ms;
+}
+
+}  // namespace bm
+
+using namespace bm;
+
+// ---------------------------------------------------------------------------
+// public entry points
+
+extern "C" {
+
+bm_status bm_default_options(bm_options* opt) {
+  if (!opt) return set_error(BM_EINVAL, "opt is NULL");
+  defaults(opt);
+  return BM_OK;
+}
+
+const char* bm_last_error(void) { return g_err; }
+
+int32_t bm_abi_version(void) { return BM_ABI_VERSION; }
+
+bm_status bm_release_scratch(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  (void)hipDeviceSynchronize();
+  scratch_release();
+  return BM_OK;
+}
+
+bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s,
+                       int32_t n_samples, uint64_t seed, const bm_options* opt_in,
+                       float* centroids, double* sse, int32_t* labels, uint8_t* degenerate,
+                       bm_stats* stats) {
+  clear_error();
+  bm_options o;
+  bm_status st = resolve(opt_in, &o);
+  if (st != BM_OK) return st;
+  if ((st = check_sizes(n, d, k, s)) != BM_OK) return st;
+  if (n_samples < 1) return set_error(BM_EINVAL, "n_samples must be >= 1");
+  if (!X || !centroids) return set_error(BM_EINVAL, "X and centroids are required");
+  if (o.resume && !degenerate) return set_error(BM_EINVAL, "resume needs the degenerate flags");
+  if (static_cast<int64_t>(o.t_start) + n_samples > 4294967295LL)
+    return set_error(BM_EINVAL, "sample indices exceed 2^32");
+  if (stats && stats->struct_size != sizeof(bm_stats))
+    return set_error(BM_EINVAL, "bm_stats.struct_size mismatch");
+  hipStream_t stream = static_cast<hipStream_t>(o.stream);
+
+  std::lock_guard<std::mutex> lock(g_mu);
+  SolverPlan sp;
+  if ((st = plan_solver(d, k, s, n, o.grid, &sp)) != BM_OK) return st;
+
+  const bool final_pass = sse || labels;
+  const int final_grid = final_pass ? assign_grid(n) : 0;
+  SolverBuffers b;
+  memset(&b.a, 0, sizeof b.a);
+  if ((st = prepare_solver(stream, s, d, k, n_samples, sp.cand_cap, true, true, true, true,
+                           final_grid, &b)) != BM_OK)
+    return st;
+  SolverArgs& a = b.a;
+  a.X = X;
+  a.n = n;
+  a.s = s;
+  a.d = d;
+  a.k = k;
+  a.x_bf16 = o.x_dtype == BM_BF16;
+  a.T = n_samples;
+  a.seed = seed;
+  a.t0 = o.t_start;
+  a.max_iter = o.max_iter;
+  a.tol = o.tol;
+  a.stop_rule = o.stop_rule;
+  a.trials = o.n_local_trials;
+  a.cmp_rule = o.compare_rule;
+  a.do_sample = 1;
+  a.do_gather = 1;
+  a.do_seed = 1;
+  a.do_lloyd = 1;
+  a.do_keep = 1;
+  a.init_incumbent = o.resume ? 0 : 1;
+  a.sums_in_lds = sp.sums_in_lds;
+  a.cand_cap = sp.cand_cap;
+  a.spin_limit = o.spin_limit ? o.spin_limit : kDefaultSpinLimit;
+  a.sample_idx_out = o.sample_idx;
+
+  if (o.resume) {
+    BM_HIP(hipMemcpyAsync(a.Cinc, centroids, sizeof(float) * size_t(k) * d, hipMemcpyDeviceToDevice, stream));
+    BM_HIP(hipMemcpyAsync(a.deg_inc, degenerate, size_t(k), hipMemcpyHostToDevice, stream));
+    BM_HIP(hipMemcpyAsync(a.f_opt, &o.f_opt_in, sizeof(double), hipMemcpyHostToDevice, stream));
+  }
+
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  for (auto& e : ev) BM_HIP(hipEventCreate(&e));
+  BM_HIP(hipEventRecord(ev[0], stream));
+  st = launch_solver(a, sp.grid, sp.lds, stream);
+  if (st != BM_OK) {
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return st;
+  }
+  BM_HIP(hipEventRecord(ev[1], stream));
+
+  // final assignment (Alg. 1 last step) over all of X
+  double sse_host = 0.0;
+  bm_status fst = BM_OK;
+  if (final_pass) {
+    fst = launch_assign(X, a.x_bf16, n, d, a.Cinc, a.deg_inc, k, labels, nullptr, b.partial,
+                        b.done, b.sse_dev, final_grid, stream);
+  }
+  BM_HIP(hipEventRecord(ev[2], stream));
+  if (final_pass && fst == BM_OK)
+    BM_HIP(hipMemcpyAsync(&sse_host, b.sse_dev, sizeof(double), hipMemcpyDeviceToHost, stream));
+
+  BM_HIP(hipMemcpyAsync(centroids, a.Cinc, sizeof(float) * size_t(k) * d, hipMemcpyDeviceToDevice, stream));
+  int64_t counters[kNumCounters];
+  double fopt = 0.0;
+  BM_HIP(hipMemcpyAsync(counters, a.counters, sizeof counters, hipMemcpyDeviceToHost, stream));
+  BM_HIP(hipMemcpyAsync(&fopt, a.f_opt, sizeof fopt, hipMemcpyDeviceToHost, stream));
+  if (degenerate)
+    BM_HIP(hipMemcpyAsync(degenerate, a.deg_inc, size_t(k), hipMemcpyDeviceToHost, stream));
+  if (o.sample_f)
+    BM_HIP(hipMemcpyAsync(o.sample_f, a.sample_f, sizeof(double) * n_samples, hipMemcpyDeviceToHost, stream));
+  int32_t code = 0;
+  st = check_solver_error(a, stream, &code);
+  const float ms_solver = elapsed_ms(ev[0], ev[1]);
+  const float ms_final = elapsed_ms(ev[1], ev[2]);
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (st != BM_OK) return st;
+  if (fst != BM_OK) return fst;
+  if (sse) *sse = sse_host;
+  if (stats) {
+    stats->samples = static_cast<int32_t>(counters[kCntSamples]);
+    stats->replacements = static_cast<int32_t>(counters[kCntReplaced]);
+    stats->grid = sp.grid;
+    stats->lloyd_iters = counters[kCntPasses];
+    stats->reseeded = counters[kCntReseeded];
+    stats->n_d = counters[kCntND];
+    stats->boundary_draws = counters[kCntBoundary];
+    stats->f_opt = fopt;
+    stats->ms_solver = ms_solver;
+    stats->ms_final = ms_final;
+  }
+  return BM_OK;
+}
+
+bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, const uint8_t* deg,
+                        int32_t k, const bm_options* opt_in, int32_t* labels, float* min_d2,
+                        double* sse) {
+  clear_error();
+  bm_options o;
+  bm_status st = resolve(opt_in, &o);
+  if (st != BM_OK) return st;
+  if (n < 1 || n > 2147483647LL || d < 1 || k < 1)
+    return set_error(BM_EINVAL, "bad sizes n=%lld d=%d k=%d", (long long)n, d, k);
+  if (!X || !C) return set_error(BM_EINVAL, "X and C are required");
+  if (deg) {
+    int active = 0;
+    for (int j = 0; j < k; ++j) active += deg[j] ? 0 : 1;
+    if (!active) return set_error(BM_EINVAL, "every centroid is degenerate");
+  }
+  if (padded_dim(d) < 0) return set_error(BM_ENOTSUP, "d = %d exceeds the limit of 256", d);
+  hipStream_t stream = static_cast<hipStream_t>(o.stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  const int grid = assign_grid(n);
+  uint8_t* deg_p = nullptr;
+  double* partial_p = nullptr;
+  unsigned int* done_p = nullptr;
+  double* sse_p = nullptr;
+  char* base = nullptr;
+  for (int round = 0; round < 2; ++round) {
+    Layout L;
+    L.base = base;
+    deg_p = L.take<uint8_t>(k);
+    partial_p = L.take<double>(grid);
+    done_p = L.take<unsigned int>(1);
+    sse_p = L.take<double>(1);
+    if (round == 0) {
+      bm_status st2 = BM_OK;
+      base = static_cast<char*>(scratch_get(L.off + 256, stream, &st2));
+      if (!base) return st2;
+    }
+  }
+  if (deg) BM_HIP(hipMemcpyAsync(deg_p, deg, size_t(k), hipMemcpyHostToDevice, stream));
+  BM_HIP(hipMemsetAsync(done_p, 0, sizeof(unsigned int), stream));
+  st = launch_assign(X, o.x_dtype == BM_BF16, n, d, C, deg ? deg_p : nullptr, k, labels, min_d2,
+                     partial_p, done_p, sse_p, grid, stream);
+  if (st != BM_OK) return st;
+  double v = 0.0;
+  BM_HIP(hipMemcpyAsync(&v, sse_p, sizeof v, hipMemcpyDeviceToHost, stream));
+  BM_HIP(hipStreamSynchronize(stream));
+  if (sse) *sse = v;
+  return BM_OK;
+}
+
+static bm_status run_solver_on_sample(const float* P, int64_t s, int32_t d, int32_t k, float* C,
+                                      uint8_t* deg, uint64_t seed, uint32_t t, bool seed_only,
+                                      const bm_options& o, int32_t* labels, double* f,
+                                      int32_t* passes) {
+  hipStream_t stream = static_cast<hipStream_t>(o.stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  SolverPlan sp;
+  bm_status st = plan_solver(d, k, s, 2 * s, o.grid, &sp);
+  if (st != BM_OK) return st;
+  SolverBuffers b;
+  memset(&b.a, 0, sizeof b.a);
+  b.a.P = const_cast<float*>(P);
+  b.a.Cinc = C;
+  b.a.labels = labels;
+  if ((st = prepare_solver(stream, s, d, k, 1, sp.cand_cap, false, true, labels == nullptr, false,
+                           0, &b)) != BM_OK)
+    return st;
+  SolverArgs& a = b.a;
+  a.X = nullptr;
+  a.n = s;
+  a.s = s;
+  a.d = d;
+  a.k = k;
+  a.T = 1;
+  a.seed = seed;
+  a.t0 = static_cast<int32_t>(t);
+  a.max_iter = o.max_iter;
+  a.tol = o.tol;
+  a.stop_rule = o.stop_rule;
+  a.trials = o.n_local_trials;
+  a.cmp_rule = BM_CMP_FOPT;
+  a.do_seed = seed_only ? 1 : 0;
+  a.do_lloyd = seed_only ? 0 : 1;
+  a.sums_in_lds = sp.sums_in_lds;
+  a.cand_cap = sp.cand_cap;
+  a.spin_limit = o.spin_limit ? o.spin_limit : kDefaultSpinLimit;
+  BM_HIP(hipMemcpyAsync(a.deg_inc, deg, size_t(k), hipMemcpyHostToDevice, stream));
+  if ((st = launch_solver(a, sp.grid, sp.lds, stream)) != BM_OK) return st;
+  int64_t counters[kNumCounters];
+  double fv = 0.0;
+  BM_HIP(hipMemcpyAsync(deg, a.deg_inc, size_t(k), hipMemcpyDeviceToHost, stream));
+  BM_HIP(hipMemcpyAsync(counters, a.counters, sizeof counters, hipMemcpyDeviceToHost, stream));
+  BM_HIP(hipMemcpyAsync(&fv, a.sample_f, sizeof fv, hipMemcpyDeviceToHost, stream));
+  if ((st = check_solver_error(a, stream, nullptr)) != BM_OK) return st;
+  if (f) *f = fv;
+  if (passes) *passes = static_cast<int32_t>(counters[kCntPasses]);
+  return BM_OK;
+}
+
+bm_status kmeanspp_seed(const float* P, int64_t s, int32_t d, int32_t k, float* C, uint8_t* deg,
+                        uint64_t seed, uint64_t stream_id, const bm_options* opt_in) {
+  clear_error();
+  bm_options o;
+  bm_status st = resolve(opt_in, &o);
+  if (st != BM_OK) return st;
+  if (s < 1 || s > 2147483647LL || d < 1 || k < 1)
+    return set_error(BM_EINVAL, "bad sizes s=%lld d=%d k=%d", (long long)s, d, k);
+  if (!P || !C || !deg) return set_error(BM_EINVAL, "P, C and deg are required");
+  if (stream_id > 0xffffffffull) return set_error(BM_EINVAL, "stream_id must be < 2^32");
+  return run_solver_on_sample(P, s, d, k, C, deg, seed, static_cast<uint32_t>(stream_id), true, o,
+                              nullptr, nullptr, nullptr);
+}
+
+bm_status kmeans_lloyd(const float* P, int64_t s, int32_t d, int32_t k, float* C, uint8_t* deg,
+                       const bm_options* opt_in, int32_t* labels, double* f, int32_t* passes) {
+  clear_error();
+  bm_options o;
+  bm_status st = resolve(opt_in, &o);
+  if (st != BM_OK) return st;
+  if (s < 1 || s > 2147483647LL || d < 1 || k < 1)
+    return set_error(BM_EINVAL, "bad sizes s=%lld d=%d k=%d", (long long)s, d, k);
+  if (!P || !C || !deg) return set_error(BM_EINVAL, "P, C and deg are required");
+  int active = 0;
+  for (int j = 0; j < k; ++j) active += deg[j] ? 0 : 1;
+  if (!active) return set_error(BM_EINVAL, "every centroid is degenerate");
+  return run_solver_on_sample(P, s, d, k, C, deg, 0, 0, false, o, labels, f, passes);
+}
+
+bm_status bm_sample_indices(int64_t n, int64_t s, uint64_t seed, int32_t t, int32_t* idx,
+                            const bm_options* opt_in) {
+  clear_error();
+  bm_options o;
+  bm_status st = resolve(opt_in, &o);
+  if (st != BM_OK) return st;
+  if (n < 1 || n > 2147483647LL || s < 1 || s > n)
+    return set_error(BM_EINVAL, "need 1 <= s <= n < 2^31 (s=%lld, n=%lld)", (long long)s, (long long)n);
+  if (t < 0) return set_error(BM_EINVAL, "t must be >= 0");
+  if (!idx) return set_error(BM_EINVAL, "idx is required");
+  hipStream_t stream = static_cast<hipStream_t>(o.stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  SolverPlan sp;
+  if ((st = plan_solver(1, 1, s, n, o.grid, &sp)) != BM_OK) return st;
+  SolverBuffers b;
+  memset(&b.a, 0, sizeof b.a);
+  b.a.idx = idx;
+  if ((st = prepare_solver(stream, s, 1, 1, 1, sp.cand_cap, false, false, true, true, 0, &b)) != BM_OK)
+    return st;
+  SolverArgs& a = b.a;
+  a.n = n;
+  a.s = s;
+  a.d = 1;
+  a.k = 1;
+  a.T = 1;
+  a.seed = seed;
+  a.t0 = t;
+  a.max_iter = 1;
+  a.trials = 1;
+  a.do_sample = 1;
+  a.cand_cap = sp.cand_cap;
+  a.sums_in_lds = sp.sums_in_lds;
+  a.spin_limit = o.spin_limit ? o.spin_limit : kDefaultSpinLimit;
+  if ((st = launch_solver(a, sp.grid, sp.lds, stream)) != BM_OK) return st;
+  return check_solver_error(a, stream, nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// bm_assign.hip -- the final assignment pass of Big-means (Alg. 1 / Sec. 3.4)
+// and the kmeans_assign entry point: every row of X goes to its nearest
+// non-degenerate centroid, and the objective of Eq. (1) is summed in FP64.
+//
+// A grid of a few workgroups per CU streams X once from HBM (each thread owns
+// whole rows, held in registers); the centroids sit in LDS, padded with zeros
+// to a multiple of 4 columns so the inner loop reads them as broadcast
+// 16-byte LDS loads.  The nearest centroid is chosen with FP32 direct
+// differences (FMA chain in dimension order; exact ties to the lowest index);
+// the chosen distance is then recomputed in FP64 for the objective.  Each workgroup
+// writes its FP64 partial objective; the last workgroup to finish adds the
+// partials in workgroup order, so the result does not depend on timing.
+#include "bm_internal.h"
+
+namespace bm {
+
+namespace {
+
+constexpr int kAssignBlock = 256;
+
+template <int DM, bool BF16>
+__global__ void __launch_bounds__(kAssignBlock)
+    assign_kernel(const void* __restrict__ Xv, int64_t n, int d, const float* __restrict__ C,
+                  const uint8_t* __restrict__ deg, int k, int32_t* __restrict__ labels,
+                  float* __restrict__ min_d2, double* __restrict__ partial,
+                  unsigned int* __restrict__ done, double* __restrict__ sse_out) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  float* Cl = reinterpret_cast<float*>(lds_raw);
+  int* act = reinterpret_cast<int*>(lds_raw + sizeof(float) * static_cast<size_t>(k) * DM);
+  __shared__ int s_na;
+  __shared__ double s_tmp[kAssignBlock / kWave + 1];
+  __shared__ int s_last;
+
+  const int tid = threadIdx.x;
+  for (int e = tid; e < k * DM; e += kAssignBlock) {
+    const int j = e / DM;
+    const int t = e - j * DM;
+    Cl[e] = (t < d) ? C[static_cast<size_t>(j) * d + t] : 0.f;
+  }
+  if (tid == 0) {
+    int na = 0;
+    for (int j = 0; j < k; ++j)
+      if (!deg || !deg[j]) act[na++] = j;
+    s_na = na;
+  }
+  __syncthreads();
+  const int na = s_na;
+
+  double sse = 0.0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kAssignBlock;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kAssignBlock + tid; i < n; i += stride) {
+    float x[DM];
+    if (BF16) {
+      load_row_bf16<DM>(static_cast<const uint16_t*>(Xv) + static_cast<size_t>(i) * d, d, x);
+    } else {
+      load_row_f32<DM>(static_cast<const float*>(Xv) + static_cast<size_t>(i) * d, d, x);
+    }
+    int bj;
+    float bd;
+    nearest_f32<DM>(x, Cl, act, na, bj, bd);
+    const double exact = dist2_f64_row<DM>(x, Cl + bj * DM);
+    if (labels) labels[i] = bj;
+    if (min_d2) min_d2[i] = static_cast<float>(exact);
+    sse += exact;
+  }
+  const double bsum = block_sum_f64<kAssignBlock>(sse, s_tmp);
+  if (tid == 0) {
+    partial[blockIdx.x] = bsum;
+    __threadfence();
+    const unsigned int prev = atomicAdd(done, 1u);
+    s_last = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (s_last && tid == 0) {
+    __threadfence();
+    double total = 0.0;
+    for (unsigned int b = 0; b < gridDim.x; ++b)
+      total += __hip_atomic_load(&partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *sse_out = total;
+    __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <int DM>
+const void* assign_fn(bool bf16) {
+  return bf16 ? reinterpret_cast<const void*>(&assign_kernel<DM, true>)
+              : reinterpret_cast<const void*>(&assign_kernel<DM, false>);
+}
+
+const void* pick_assign(int dm, bool bf16) {
+  switch (dm) {
+    case 4: return assign_fn<4>(bf16);
+    case 8: return assign_fn<8>(bf16);
+    case 16: return assign_fn<16>(bf16);
+    case 32: return assign_fn<32>(bf16);
+    case 64: return assign_fn<64>(bf16);
+    case 72: return assign_fn<72>(bf16);
+    case 128: return assign_fn<128>(bf16);
+    case 256: return assign_fn<256>(bf16);
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+int assign_grid(int64_t n) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t want = (n + kAssignBlock - 1) / kAssignBlock;
+  const int64_t cap = static_cast<int64_t>(cus) * 8;
+  int64_t g = want < cap ? want : cap;
+  return static_cast<int>(g < 1 ? 1 : g);
+}
+
+bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float* C,
+                        const uint8_t* deg_dev, int k, int32_t* labels, float* min_d2,
+                        double* partial, unsigned int* done, double* sse_dev, int grid,
+                        hipStream_t stream) {
+  const int dm = padded_dim(d);
+  const void* fn = pick_assign(dm, x_bf16 != 0);
+  if (!fn) return set_error(BM_ENOTSUP, "dimension %d exceeds the assign kernel's limit of 256", d);
+  const size_t lds = sizeof(float) * static_cast<size_t>(k) * dm + sizeof(int) * static_cast<size_t>(k);
+  size_t lds_max = 0;
+  bm_status st = max_lds_per_block(&lds_max);
+  if (st != BM_OK) return st;
+  if (lds + 1024 > lds_max)
+    return set_error(BM_ENOTSUP, "k*d = %d*%d centroids do not fit in LDS", k, d);
+  void* args[] = {const_cast<void**>(&X), &n, &d, const_cast<float**>(&C),
+                  const_cast<uint8_t**>(&deg_dev), &k, &labels, &min_d2, &partial, &done,
+                  &sse_dev};
+  const hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kAssignBlock), args, lds, stream);
+  if (e != hipSuccess)
+    return set_error(BM_EDEVICE, "assign launch failed: %s", hipGetErrorString(e));
+  return BM_OK;
+}
+
+}  // namespace bm

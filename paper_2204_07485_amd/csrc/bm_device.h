@@ -1,0 +1,269 @@
+// bm_device.h -- device building blocks shared by the library's kernels:
+// a bounded grid barrier for cooperative launches, block-wide scans and
+// reductions for 64-wide wavefronts, and the direct-difference distances.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bm {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 512;                 // solver workgroup: 8 wavefronts
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// ---------------------------------------------------------------------------
+// Grid barrier for a cooperative launch (every workgroup is resident).
+// Arrival counter plus generation word; the last arriver resets the counter
+// and publishes the next generation.  A waiter that polls more than
+// spin_limit times raises `abort`, and every later barrier returns false at
+// once, so a logic error ends the kernel instead of hanging it.
+struct GridBarrier {
+  unsigned int arrive;
+  unsigned int gen;
+  int abort;
+  int pad;
+};
+
+__device__ __forceinline__ bool grid_barrier(GridBarrier* b, unsigned int nblocks,
+                                             unsigned int spin_limit) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      ok = 0;
+    } else {
+      const unsigned int g =
+          __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      const unsigned int prev =
+          __hip_atomic_fetch_add(&b->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (prev == nblocks - 1) {
+        __hip_atomic_store(&b->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&b->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        unsigned int polls = 0;
+        while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+          if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            ok = 0;
+            break;
+          }
+          if (++polls > spin_limit) {
+            __hip_atomic_store(&b->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __threadfence();
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide primitives for blockDim.x == BLOCK (a multiple of 64).  `tmp` is
+// LDS scratch of at least BLOCK/64 + 1 elements; every thread must call.
+
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* tmp, T& total) {
+  constexpr int NW = BLOCK / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  T incl = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const T y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  if (lane == kWave - 1) tmp[wave] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T run = T(0);
+    for (int w = 0; w < NW; ++w) {
+      const T x = tmp[w];
+      tmp[w] = run;
+      run += x;
+    }
+    tmp[NW] = run;
+  }
+  __syncthreads();
+  const T excl = incl - v + tmp[wave];
+  total = tmp[NW];
+  __syncthreads();
+  return excl;
+}
+
+// Inclusive scan in FP64 with a fixed combination order (wave tree, then
+// waves in order).
+template <int BLOCK>
+__device__ __forceinline__ double block_inclusive_scan_f64(double v, double* tmp, double& total) {
+  constexpr int NW = BLOCK / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  double incl = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const double y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  if (lane == kWave - 1) tmp[wave] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      const double x = tmp[w];
+      tmp[w] = run;
+      run += x;
+    }
+    tmp[NW] = run;
+  }
+  __syncthreads();
+  const double out = incl + tmp[wave];
+  total = tmp[NW];
+  __syncthreads();
+  return out;
+}
+
+// Sum over the block in a fixed order; the result is returned to every thread.
+template <int BLOCK>
+__device__ __forceinline__ double block_sum_f64(double v, double* tmp) {
+  constexpr int NW = BLOCK / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+  if (lane == 0) tmp[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    for (int w = 0; w < NW; ++w) run += tmp[w];
+    tmp[NW] = run;
+  }
+  __syncthreads();
+  const double r = tmp[NW];
+  __syncthreads();
+  return r;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ int block_sum_i32(int v, int* tmp) {
+  constexpr int NW = BLOCK / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+  if (lane == 0) tmp[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < NW; ++w) run += tmp[w];
+    tmp[NW] = run;
+  }
+  __syncthreads();
+  const int r = tmp[NW];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Element loads: FP32, or BF16 bit patterns widened exactly to FP32.
+__device__ __forceinline__ float bf16_bits_to_float(uint16_t h) {
+  return __uint_as_float(static_cast<unsigned int>(h) << 16);
+}
+
+// Load row `r` (d elements) into registers x[DM], zero-filled past d.
+template <int DM>
+__device__ __forceinline__ void load_row_f32(const float* __restrict__ r, int d, float (&x)[DM]) {
+  if ((d & 3) == 0) {
+    const float4* r4 = reinterpret_cast<const float4*>(r);
+#pragma unroll
+    for (int q = 0; q < DM / 4; ++q) {
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (4 * q < d) v = r4[q];
+      x[4 * q + 0] = v.x;
+      x[4 * q + 1] = v.y;
+      x[4 * q + 2] = v.z;
+      x[4 * q + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < DM; ++t) x[t] = (t < d) ? r[t] : 0.f;
+  }
+}
+
+template <int DM>
+__device__ __forceinline__ void load_row_bf16(const uint16_t* __restrict__ r, int d,
+                                              float (&x)[DM]) {
+#pragma unroll
+  for (int t = 0; t < DM; ++t) x[t] = (t < d) ? bf16_bits_to_float(r[t]) : 0.f;
+}
+
+// Squared distance in FP32 by direct differences, FMA in dimension order,
+// against a centroid row padded with zeros to DM (the padding adds exact 0).
+template <int DM>
+__device__ __forceinline__ float dist2_f32(const float (&x)[DM], const float* __restrict__ c) {
+  float acc = 0.f;
+#pragma unroll
+  for (int t = 0; t < DM; t += 4) {
+    const float4 cv = *reinterpret_cast<const float4*>(c + t);
+    float e = x[t + 0] - cv.x;
+    acc = __builtin_fmaf(e, e, acc);
+    e = x[t + 1] - cv.y;
+    acc = __builtin_fmaf(e, e, acc);
+    e = x[t + 2] - cv.z;
+    acc = __builtin_fmaf(e, e, acc);
+    e = x[t + 3] - cv.w;
+    acc = __builtin_fmaf(e, e, acc);
+  }
+  return acc;
+}
+
+// Nearest active centroid: `act` lists the na active slots in ascending order,
+// so a strict comparison keeps the lowest index on exact ties.
+template <int DM>
+__device__ __forceinline__ void nearest_f32(const float (&x)[DM], const float* __restrict__ Cl,
+                                            const int* __restrict__ act, int na, int& best_j,
+                                            float& best_d) {
+  best_j = -1;
+  best_d = __builtin_inff();
+  for (int a = 0; a < na; ++a) {
+    const int j = act[a];
+    const float v = dist2_f32<DM>(x, Cl + j * DM);
+    if (v < best_d) {
+      best_d = v;
+      best_j = j;
+    }
+  }
+}
+
+// Squared distance in FP64 of a register row to a padded LDS row (the
+// objective of the chosen centroid; padding contributes exact zeros).
+template <int DM>
+__device__ __forceinline__ double dist2_f64_row(const float (&x)[DM], const float* __restrict__ c) {
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < DM; ++t) {
+    const double e = static_cast<double>(x[t]) - static_cast<double>(c[t]);
+    acc = __builtin_fma(e, e, acc);
+  }
+  return acc;
+}
+
+// Squared distance in FP64 by direct differences of FP32 values, FMA in
+// dimension order (used where the result steers a random draw).
+__device__ __forceinline__ double dist2_f64(const float* __restrict__ a,
+                                            const float* __restrict__ b, int d) {
+  double acc = 0.0;
+  for (int t = 0; t < d; ++t) {
+    const double e = static_cast<double>(a[t]) - static_cast<double>(b[t]);
+    acc = __builtin_fma(e, e, acc);
+  }
+  return acc;
+}
+
+}  // namespace bm

@@ -1,0 +1,114 @@
+// bm_internal.h -- declarations shared by the library's translation units
+// (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bigmeans.h"
+#include "bm_device.h"
+
+namespace bm {
+
+constexpr int kMaxTrials = 8;       // K-means++ candidates per centre
+constexpr int kMaxGrid = 1024;      // solver workgroups
+constexpr int kNumCounters = 16;
+constexpr unsigned int kDefaultSpinLimit = 1u << 24;
+
+enum Counter {
+  kCntPasses = 0,      // Lloyd assignment passes
+  kCntReseeded = 1,    // centroids placed by K-means++
+  kCntReplaced = 2,    // incumbent replacements
+  kCntND = 3,          // distance evaluations at sample level
+  kCntBoundary = 4,    // D^2 draws within rounding of a running-sum boundary
+  kCntSamples = 5,     // samples processed
+  kCntSelectPasses = 6 // histogram passes of the sampler (all samples)
+};
+
+enum SolverError {
+  kErrNone = 0,
+  kErrBarrier = 1,     // a grid-barrier wait exceeded its bound
+  kErrSelect = 2,      // sampler bookkeeping inconsistent
+  kErrSeed = 3,        // K-means++ found no candidate
+};
+
+// Everything the cooperative solver kernel needs; passed by value.
+struct SolverArgs {
+  const void* X;
+  int64_t n;
+  int64_t s;
+  int32_t d;
+  int32_t k;
+  int32_t x_bf16;
+  int32_t T;
+  uint64_t seed;
+  int32_t t0;
+  int32_t max_iter;
+  double tol;
+  int32_t stop_rule;
+  int32_t trials;
+  int32_t cmp_rule;
+  int32_t do_sample;
+  int32_t do_gather;
+  int32_t do_seed;
+  int32_t do_lloyd;
+  int32_t do_keep;
+  int32_t init_incumbent;
+  int32_t sums_in_lds;
+  int32_t cand_cap;          // power of two, <= what the LDS sort buffer holds
+  uint32_t spin_limit;
+  // sample-sized buffers
+  float* P;                  // s x d
+  int32_t* idx;              // s
+  int32_t* labels;           // s
+  double* w;                 // s (K-means++ D^2 weights)
+  // incumbent
+  float* Cinc;               // k x d
+  uint8_t* deg_inc;          // k
+  double* f_opt;             // 1
+  // reductions
+  double* c64;               // 2 x k x d: FP64 centroid means (old / new)
+  double* sums;              // 3 x k x d ring
+  int32_t* cnt;              // 3 x k ring
+  double* sse_part;          // 2 x kMaxGrid
+  double* wsum;              // kMaxGrid
+  double* phi_part;          // kMaxGrid x kMaxTrials
+  int64_t* cand;             // kMaxTrials
+  // sampler
+  uint32_t* hist;            // 3 x 256 ring
+  uint32_t* wg_lo;           // kMaxGrid
+  uint32_t* wg_off;          // kMaxGrid
+  uint64_t* cand_key;        // cand_cap
+  int32_t* cand_idx;         // cand_cap
+  uint32_t* cand_count;      // 1
+  uint64_t* thr;             // 2: threshold key, index
+  // outputs / control
+  int32_t* sample_idx_out;   // T x s or null
+  double* sample_f;          // T
+  int64_t* counters;         // kNumCounters
+  GridBarrier* bar;
+  int32_t* err;
+};
+
+// Device scratch pool (per process, current device); grows on demand.
+void* scratch_get(size_t bytes, hipStream_t stream, bm_status* st);
+void scratch_release();
+
+// Error reporting for the ABI layer.
+bm_status set_error(bm_status code, const char* fmt, ...);
+void clear_error();
+
+// Launchers (defined in bm_solver.hip / bm_assign.hip).
+size_t solver_lds_bytes(int dm, int k, int d, int grid, int cand_cap, bool sums_in_lds);
+int padded_dim(int d);
+bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t stream);
+bm_status solver_max_grid(int dm, size_t lds, int* max_grid);
+bm_status max_lds_per_block(size_t* bytes);
+
+bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float* C,
+                        const uint8_t* deg_dev, int k, int32_t* labels, float* min_d2,
+                        double* partial, unsigned int* done, double* sse_dev, int grid,
+                        hipStream_t stream);
+int assign_grid(int64_t n);
+
+}  // namespace bm

@@ -1,0 +1,114 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/bigmeans.h declares, and rejects invalid arguments with
+BM_EINVAL before touching the device."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bigmeans.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:bm_status|const char\*|int32_t)\s+(\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def bm():
+    from paper_2204_07485_amd import bigmeans
+    return bigmeans
+
+
+def test_library_exports_every_declared_function(bm):
+    lib = bm.load()
+    names = _declared_functions()
+    assert {"bigmeans_fit", "kmeans_assign", "kmeanspp_seed"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(bm.FUNCTIONS)
+
+
+def test_abi_version_and_struct_sizes(bm):
+    lib = bm.load()
+    assert lib.bm_abi_version() == 1
+    o = bm.Options()
+    assert lib.bm_default_options(ct.byref(o)) == 0
+    assert o.struct_size == ct.sizeof(bm.Options)
+    assert o.max_iter == 100 and o.n_local_trials == 3 and abs(o.tol - 1e-4) < 1e-18
+
+
+def _fit(bm, n=10, d=2, k=2, s=5, T=1, X=1, C=1, opt=None, deg=None):
+    lib = bm.load()
+    sse = ct.c_double()
+    return lib.bigmeans_fit(ct.c_void_p(X), n, d, k, s, T, ct.c_uint64(1),
+                            None if opt is None else ct.byref(opt), ct.c_void_p(C),
+                            ct.byref(sse), None, deg, None)
+
+
+@pytest.mark.parametrize("kw", [dict(k=6, s=5), dict(s=11), dict(d=0), dict(n=0, s=0, k=0),
+                                dict(T=0), dict(X=0), dict(C=0), dict(n=2**31, s=5)])
+def test_fit_rejects_invalid_sizes(bm, kw):
+    assert _fit(bm, **kw) == bm.BM_EINVAL
+    assert bm.load().bm_last_error()
+
+
+@pytest.mark.parametrize("field,value", [("max_iter", 0), ("n_local_trials", 0),
+                                         ("n_local_trials", 9), ("stop_rule", 7),
+                                         ("compare_rule", 5), ("x_dtype", 3), ("tol", -1.0),
+                                         ("grid", 5000), ("struct_size", 3)])
+def test_fit_rejects_invalid_options(bm, field, value):
+    o = bm.Options()
+    bm.load().bm_default_options(ct.byref(o))
+    setattr(o, field, value)
+    assert _fit(bm, opt=o) == bm.BM_EINVAL
+
+
+def test_resume_requires_flags(bm):
+    o = bm.Options()
+    bm.load().bm_default_options(ct.byref(o))
+    o.resume = 1
+    assert _fit(bm, opt=o) == bm.BM_EINVAL
+
+
+def test_other_entry_points_reject_invalid_arguments(bm):
+    lib = bm.load()
+    deg = np.ones(3, np.uint8)
+    p = deg.ctypes.data_as(ct.c_void_p)
+    assert lib.kmeans_assign(ct.c_void_p(1), 0, 2, ct.c_void_p(1), None, 2, None, None, None, None) == bm.BM_EINVAL
+    assert lib.kmeans_assign(ct.c_void_p(1), 5, 2, ct.c_void_p(1), p, 3, None, None, None, None) == bm.BM_EINVAL
+    assert lib.kmeanspp_seed(None, 5, 2, 3, ct.c_void_p(1), p, ct.c_uint64(1), ct.c_uint64(0), None) == bm.BM_EINVAL
+    assert lib.kmeanspp_seed(ct.c_void_p(1), 5, 2, 3, ct.c_void_p(1), p, ct.c_uint64(1), ct.c_uint64(2**32), None) == bm.BM_EINVAL
+    assert lib.kmeans_lloyd(ct.c_void_p(1), 5, 2, 3, ct.c_void_p(1), p, None, None, None, None) == bm.BM_EINVAL
+    assert lib.bm_sample_indices(5, 6, ct.c_uint64(1), 0, ct.c_void_p(1), None) == bm.BM_EINVAL
+    assert lib.bm_sample_indices(5, 3, ct.c_uint64(1), -1, ct.c_void_p(1), None) == bm.BM_EINVAL
+    assert lib.bm_default_options(None) == bm.BM_EINVAL
+
+
+def test_product_philox_matches_oracle_on_host():
+    # the GPU library's generator header compiled for the host, against the
+    # oracle's independent implementation, on 10^6 counters
+    import subprocess
+    import oracle
+    src = os.path.join(ROOT, "tests", "philox_host_check.cpp")
+    exe = os.path.join(ROOT, "tests", "_build", "philox_host_check")
+    os.makedirs(os.path.dirname(exe), exist_ok=True)
+    if not os.path.exists(exe) or os.path.getmtime(exe) < max(
+            os.path.getmtime(src),
+            os.path.getmtime(os.path.join(ROOT, "paper_2204_07485_amd", "csrc", "bm_rng.h"))):
+        subprocess.run(["hipcc", "--offload-arch=gfx950", "-O2", "-std=c++17", src, "-o", exe], check=True)
+    out = subprocess.run([exe, "1000000", "12345"], capture_output=True, text=True, check=True).stdout
+    got = [int(v) for v in out.split()]
+    # the program prints an xor-fold of all sample keys and draws, plus spot values
+    seed, t = 12345, 7
+    spots = [0, 1, 999_999, 500_001]
+    want = [oracle.sample_key(seed, t, i) for i in spots] + [oracle.seed_word(seed, t, q) for q in spots]
+    assert got[:8] == want
+    fold = 0
+    for i in range(0, 1_000_000, 997):
+        fold ^= oracle.sample_key(seed, t, i) ^ oracle.seed_word(seed, t, i)
+    assert got[8] == fold

@@ -1,0 +1,159 @@
+"""End-to-end Big-means parity (Alg. 1 + final assignment) against the oracle on
+the same seeded input: sampled indices bit-exact, per-sample objectives, final
+SSE and centroids to 1e-6 relative, integer counters exact."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2204_07485_amd import synth
+from tests.parity import assert_centroids, assert_labels, assert_sse
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _compare(X, got, ref, T, exact_counters=True):
+    assert np.array_equal(got["sample_idx"].cpu().numpy(), ref["sample_idx"])
+    sf_g, sf_r = got["sample_f"], ref["sample_f"]
+    rel = np.abs(sf_g - sf_r) / sf_r
+    first_bad = int(np.argmax(rel > 1e-6)) if (rel > 1e-6).any() else None
+    assert first_bad is None, f"per-sample objective diverges first at sample {first_bad}: {rel[first_bad]:.3e}"
+    assert_sse(got["sse"], ref["sse"])
+    assert_sse(got["f_opt"], ref["f_opt"])
+    assert np.array_equal(got["degenerate"], ref["deg"])
+    assert_centroids(got["centroids"].cpu().numpy(), ref["C"], ref["deg"], X, ref["labels"])
+    assert_labels(got["labels"].cpu().numpy(), ref["labels"], X, ref["C"], ref["deg"])
+    if exact_counters:
+        gs, rs = got["stats"], ref["stats"]
+        assert gs["samples"] == rs["samples"] == T
+        assert gs["replacements"] == rs["replacements"]
+        assert gs["reseeded"] == rs["reseeded"]
+        assert gs["lloyd_iters"] == rs["lloyd_iters"]
+        assert gs["n_d"] == rs["n_d"]
+        assert gs["boundary_draws"] == 0
+
+
+def test_small_workload_matches_oracle():
+    # 20,000 x 8, 10 isotropic Gaussians, k=10, s=2,000, 20 samples,
+    # Lloyd until centroid shift < 1e-4 or 100 rounds
+    from paper_2204_07485_amd import bigmeans
+    W = synth.SMALL
+    X = synth.make_small()
+    print(f"fit small n={W.n} d={W.d} k={W.k} s={W.s} T={W.n_samples}", flush=True)
+    got = bigmeans.bigmeans_fit(torch.from_numpy(X).cuda(), W.k, W.s, W.n_samples, W.seed,
+                                sample_idx=True, max_iter=100, tol=1e-4,
+                                stop_rule=bigmeans.BM_STOP_SHIFT)
+    ref = oracle.bigmeans_fit(X, W.k, W.s, W.n_samples, W.seed, max_iter=100, tol=1e-4,
+                              stop_rule=oracle.ORC_STOP_SHIFT, want_sample_idx=True)
+    _compare(X, got, ref, W.n_samples)
+
+
+@pytest.mark.parametrize("grid", [1, 5, 64])
+def test_small_workload_any_grid(grid):
+    from paper_2204_07485_amd import bigmeans
+    X, _ = synth.gaussian_mixture(30_000, 5, 8, seed=21, sigma_range=(0.5, 2.0), weights="dirichlet")
+    print(f"fit grid={grid}", flush=True)
+    got = bigmeans.bigmeans_fit(torch.from_numpy(X).cuda(), 8, 3_001, 6, 99, sample_idx=True,
+                                grid=grid, stop_rule=bigmeans.BM_STOP_REL_OBJ, max_iter=300)
+    ref = oracle.bigmeans_fit(X, 8, 3_001, 6, 99, want_sample_idx=True,
+                              stop_rule=oracle.ORC_STOP_REL_OBJ, max_iter=300)
+    _compare(X, got, ref, 6)
+    assert got["stats"]["grid"] == min(grid, 3_001)
+
+
+def test_medium_workload_three_samples():
+    # 1,000,000 x 16, 25 components, k=25, s=40,000, paper stop rule; 3 samples
+    from paper_2204_07485_amd import bigmeans
+    W = synth.MEDIUM
+    X = synth.make_medium()
+    T = 3
+    print(f"fit medium T={T}", flush=True)
+    got = bigmeans.bigmeans_fit(torch.from_numpy(X).cuda(), W.k, W.s, T, W.seed, sample_idx=True,
+                                max_iter=300, tol=1e-4, stop_rule=bigmeans.BM_STOP_REL_OBJ)
+    ref = oracle.bigmeans_fit(X, W.k, W.s, T, W.seed, max_iter=300, tol=1e-4,
+                              stop_rule=oracle.ORC_STOP_REL_OBJ, want_sample_idx=True)
+    _compare(X, got, ref, T)
+
+
+def test_medium_workload_full_run_matches_stored_oracle():
+    # the benchmark's workload and launch configuration, against the oracle's
+    # result stored by tests/golden/make_golden.py
+    from paper_2204_07485_amd import bigmeans
+    with open(os.path.join(HERE, "golden", "medium_fit.json")) as fh:
+        gold = json.load(fh)
+    W = synth.MEDIUM
+    X = synth.make_medium()
+    got = bigmeans.bigmeans_fit(torch.from_numpy(X).cuda(), W.k, W.s, W.n_samples, W.seed,
+                                max_iter=300, tol=1e-4, stop_rule=bigmeans.BM_STOP_REL_OBJ)
+    print(f"medium full: gpu sse {got['sse']!r} oracle {gold['sse']!r}", flush=True)
+    assert_sse(got["sse"], gold["sse"])
+    assert_sse(got["f_opt"], gold["f_opt"])
+    np.testing.assert_allclose(got["sample_f"], gold["sample_f"], rtol=1e-6)
+    assert got["degenerate"].tolist() == gold["deg"]
+    assert got["stats"]["replacements"] == gold["stats"]["replacements"]
+    assert got["stats"]["lloyd_iters"] == gold["stats"]["lloyd_iters"]
+    assert got["stats"]["n_d"] == gold["stats"]["n_d"]
+    assert_centroids(got["centroids"].cpu().numpy(), np.array(gold["C"]), np.array(gold["deg"]))
+
+
+def test_resume_equals_uninterrupted():
+    from paper_2204_07485_amd import bigmeans
+    X, _ = synth.gaussian_mixture(50_000, 6, 12, seed=5, sigma_range=(0.5, 2.0), weights="dirichlet")
+    Xd = torch.from_numpy(X).cuda()
+    full = bigmeans.bigmeans_fit(Xd, 12, 4000, 9, 17)
+    first = bigmeans.bigmeans_fit(Xd, 12, 4000, 4, 17, want_labels=False, want_sse=False)
+    rest = bigmeans.bigmeans_fit(Xd, 12, 4000, 5, 17, t_start=4,
+                                 state=(first["centroids"], first["degenerate"], first["f_opt"]))
+    assert torch.equal(full["labels"], rest["labels"])
+    assert np.array_equal(full["degenerate"], rest["degenerate"])
+    assert full["sse"] == rest["sse"]
+    assert full["f_opt"] == rest["f_opt"]
+    assert np.array_equal(full["sample_f"], np.concatenate([first["sample_f"], rest["sample_f"]]))
+    a = full["centroids"].cpu().numpy()
+    b = rest["centroids"].cpu().numpy()
+    assert np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(a[~np.isnan(a)], b[~np.isnan(b)])
+
+
+def test_deterministic_integer_outputs():
+    from paper_2204_07485_amd import bigmeans
+    X = synth.make_small()
+    Xd = torch.from_numpy(X).cuda()
+    a = bigmeans.bigmeans_fit(Xd, 10, 2000, 8, 3, sample_idx=True)
+    b = bigmeans.bigmeans_fit(Xd, 10, 2000, 8, 3, sample_idx=True)
+    assert torch.equal(a["sample_idx"], b["sample_idx"])
+    assert torch.equal(a["labels"], b["labels"])
+    assert a["stats"]["lloyd_iters"] == b["stats"]["lloyd_iters"]
+
+
+def test_resample_compare_rule_matches_oracle():
+    from paper_2204_07485_amd import bigmeans
+    X, _ = synth.gaussian_mixture(40_000, 4, 6, seed=31, sigma_range=(0.5, 2.0))
+    got = bigmeans.bigmeans_fit(torch.from_numpy(X).cuda(), 6, 1500, 10, 8, sample_idx=True,
+                                compare_rule=bigmeans.BM_CMP_RESAMPLE)
+    ref = oracle.bigmeans_fit(X, 6, 1500, 10, 8, want_sample_idx=True,
+                              compare_rule=oracle.ORC_CMP_RESAMPLE)
+    _compare(X, got, ref, 10)
+
+
+def test_bf16_input_matches_oracle():
+    from paper_2204_07485_amd import bigmeans
+    X, _ = synth.gaussian_mixture(60_000, 32, 10, seed=13, sigma_range=(0.5, 2.0), outlier_frac=0.1)
+    H = synth.to_bf16_bits(X)
+    got = bigmeans.bigmeans_fit(torch.from_numpy(H.view(np.int16)).cuda(), 10, 5000, 4, 2,
+                                sample_idx=True, stop_rule=bigmeans.BM_STOP_REL_OBJ, max_iter=300)
+    ref = oracle.bigmeans_fit(H, 10, 5000, 4, 2, want_sample_idx=True,
+                              stop_rule=oracle.ORC_STOP_REL_OBJ, max_iter=300)
+    _compare(synth.bf16_bits_to_f32(H), got, ref, 4)
+
+
+def test_k_equals_s_equals_n():
+    from paper_2204_07485_amd import bigmeans
+    X = np.arange(24, dtype=np.float32).reshape(12, 2)
+    got = bigmeans.bigmeans_fit(torch.from_numpy(X).cuda(), 12, 12, 2, 1)
+    assert got["sse"] == 0.0
+    assert not got["degenerate"].any()
