@@ -1,13 +1,23 @@
 """GPU K-means (Lloyd) parity (Sec. 2; empty clusters turn degenerate, Sec. 3.3;
 stop rules of Sec. 5 and the shift rule).  Same FP32 sample and start
-centroids on both sides."""
+centroids on both sides.
+
+A single near-tie label flip (a point whose two nearest centroids are within
+FP32 resolution) moves a centroid by |x - c| / |cluster| and changes every
+later step, so the comparison runs in lock-step: at every step of the
+oracle's trajectory the GPU is started from the oracle's centroids, its
+assignment must equal the oracle's except at near ties, and its new centroids
+must equal the FP64 means of its own assignment (and the oracle's new
+centroids when the assignments agree).  The whole-run result must match the
+oracle exactly when the oracle's trajectory never comes within the near-tie
+band."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from paper_2204_07485_amd import synth
-from tests.parity import assert_centroids, assert_labels, assert_sse, top2_gap
+from tests.parity import LABEL_TIE_REL, assert_centroids, assert_labels, assert_sse, top2_gap
 
 pytestmark = pytest.mark.gpu
 
@@ -17,6 +27,58 @@ def _gpu_lloyd(P, C, deg, **kw):
     Cd = torch.from_numpy(np.ascontiguousarray(C, np.float32)).cuda()
     dg, lab, f, passes = bigmeans.kmeans_lloyd(torch.from_numpy(P).cuda(), Cd, deg, **kw)
     return Cd.cpu().numpy(), dg, lab.cpu().numpy(), f, passes
+
+
+def _gpu_assign(P, C, deg):
+    from paper_2204_07485_amd import bigmeans
+    lab, _, f = bigmeans.kmeans_assign(torch.from_numpy(P).cuda(),
+                                       torch.from_numpy(np.ascontiguousarray(C, np.float32)).cuda(),
+                                       deg)
+    return lab.cpu().numpy(), f
+
+
+def _means(P, lab, k, deg):
+    P64 = P.astype(np.float64)
+    C = np.full((k, P.shape[1]), np.nan)
+    new_deg = np.array(deg, np.uint8, copy=True)
+    for j in range(k):
+        if deg[j]:
+            continue
+        m = lab == j
+        if m.any():
+            C[j] = P64[m].mean(axis=0)
+        else:
+            new_deg[j] = 1
+    return C, new_deg
+
+
+def lockstep(P, C0, deg0, steps):
+    """Walk the oracle's trajectory; check every GPU step against it.
+    Returns the smallest relative top-2 gap met along the way."""
+    k = len(C0)
+    C = np.asarray(C0, np.float64)
+    deg = np.array(deg0, np.uint8)
+    min_gap = np.inf
+    for step in range(steps):
+        C32 = C.astype(np.float32)
+        min_gap = min(min_gap, float(top2_gap(P, C32, deg).min()))
+        lab_o = oracle.assign(P, C32, deg)[0]
+        lab_g, _ = _gpu_assign(P, C32, deg)
+        assert_labels(lab_g, lab_o, P, C32, deg)
+        gC, gdeg, _, _, gp = _gpu_lloyd(P, C32, deg, max_iter=1, tol=0.0)
+        assert gp == 2
+        # the update is the exact mean of the GPU's own assignment
+        mC, mdeg = _means(P, lab_g, k, deg)
+        assert np.array_equal(gdeg, mdeg), f"step {step}: degenerate flags"
+        assert_centroids(gC, mC, mdeg, P, lab_g)
+        rC, rdeg, _, _, _, _ = oracle.lloyd(P, C32, deg, max_iter=1, tol=0.0)
+        if np.array_equal(lab_g, lab_o):
+            assert np.array_equal(gdeg, rdeg)
+            assert_centroids(gC, rC, rdeg, P, lab_o)
+        if np.allclose(rC, C, equal_nan=True, rtol=0, atol=0):
+            break
+        C, deg = rC, rdeg
+    return min_gap
 
 
 @pytest.mark.parametrize("s,d,k,rule,grid", [(2000, 8, 10, 0, 0), (40_000, 16, 25, 1, 0),
@@ -33,33 +95,40 @@ def test_lloyd_matches_oracle(s, d, k, rule, grid):
     gC, gdeg, glab, gf, gp = _gpu_lloyd(P, C0, deg, max_iter=max_iter, tol=1e-4, stop_rule=rule,
                                          grid=grid)
     rC, rdeg, rlab, rf, rp, _ = oracle.lloyd(P, C0, deg, max_iter=max_iter, tol=1e-4, stop_rule=rule)
-    n_mis = assert_labels(glab, rlab, P, rC, rdeg)
-    if n_mis == 0:
-        # identical trajectory: every decision and every count agrees
+    min_gap = lockstep(P, C0, deg, steps=min(rp, 60))
+    if min_gap >= LABEL_TIE_REL:
+        # no near tie on the oracle's path: the whole run must agree
+        assert_labels(glab, rlab, P, rC, rdeg)
         assert gp == rp
         assert np.array_equal(gdeg, rdeg)
         assert_sse(gf, rf)
         assert_centroids(gC, rC, rdeg, P, rlab)
     else:
-        print(f"  {n_mis} near-tie label flips: trajectory comparison skipped", flush=True)
-        assert_sse(gf, rf, rel=1e-3)
+        print(f"  oracle path meets a near tie (gap {min_gap:.2e}); whole-run check relaxed",
+              flush=True)
+        # the GPU's own result is self-consistent: its objective is that of its
+        # centroids, its labels are their nearest centroids, and it is a local
+        # optimum of comparable quality
+        P64 = P.astype(np.float64)
+        act = ~gdeg.astype(bool)
+        own = ((P64 - gC.astype(np.float64)[glab]) ** 2).sum()
+        assert_sse(gf, own)
+        assert_labels(glab, oracle.assign(P, gC, gdeg)[0], P, gC, gdeg)
+        assert act.any()
+        assert abs(gf - rf) <= 0.05 * rf
 
 
 def test_single_step_counts_and_means_exact():
-    # one update from the same start: the cluster counts are integers and must
-    # match exactly; the means agree to the centroid tolerance
     s, d, k = 50_000, 16, 25
     P = synth.gaussian_mixture(s, d, k, seed=8, sigma_range=(0.5, 2.0))[0]
     C0 = P[:k].copy()
     deg = np.zeros(k, np.uint8)
-    if not (top2_gap(P, C0) >= 1e-5).all():
-        pytest.skip("start centroids have near-tie points")
-    gC, gdeg, glab, gf, gp = _gpu_lloyd(P, C0, deg, max_iter=1, tol=0.0)
-    rC, rdeg, rlab, rf, rp, _ = oracle.lloyd(P, C0, deg, max_iter=1, tol=0.0)
-    lab0_g = oracle.assign(P, C0)[0]
-    assert np.array_equal(gdeg, rdeg)
-    assert_centroids(gC, rC, rdeg, P, lab0_g)
-    assert gp == rp == 2
+    lab_g, _ = _gpu_assign(P, C0, deg)
+    gC, gdeg, _, _, gp = _gpu_lloyd(P, C0, deg, max_iter=1, tol=0.0)
+    mC, mdeg = _means(P, lab_g, k, deg)
+    assert np.array_equal(gdeg, mdeg)
+    assert_centroids(gC, mC, mdeg, P, lab_g)
+    assert gp == 2
 
 
 def test_empty_cluster_becomes_degenerate():
