@@ -137,8 +137,10 @@ static bm_status resolve(const bm_options* in, bm_options* out) {
 struct SolverPlan {
   int dm = 0;
   int grid = 0;
-  int cand_cap = 0;
+  int64_t cand_cap = 0;
+  uint64_t win_lo = 0, win_hi = 0;
   bool sums_in_lds = false;
+  bool c64_in_lds = false;
   size_t lds = 0;
 };
 
@@ -150,18 +152,19 @@ static bm_status plan_solver(int d, int k, int64_t s, int64_t n_points, int grid
   bm_status st = max_lds_per_block(&lds_max);
   if (st != BM_OK) return st;
   const size_t budget = lds_max > 2048 ? lds_max - 2048 : lds_max;  // static LDS of the kernel
+  // prefer, in order: FP64 sums in LDS, FP64 means in LDS
   bool found = false;
-  for (int cap = 4096; cap >= 256 && !found; cap >>= 1) {
-    for (int sl = 1; sl >= 0 && !found; --sl) {
-      const size_t need = solver_lds_bytes(sp->dm, k, d, 0, cap, sl != 0);
-      if (need <= budget) {
-        sp->cand_cap = cap;
-        sp->sums_in_lds = sl != 0;
-        sp->lds = need;
-        found = true;
-      }
+  for (int mode = 3; mode >= 0 && !found; --mode) {
+    const bool sl = (mode & 2) != 0, cl = (mode & 1) != 0;
+    const size_t need = solver_lds_bytes(sp->dm, k, d, sl, cl);
+    if (need <= budget) {
+      sp->sums_in_lds = sl;
+      sp->c64_in_lds = cl;
+      sp->lds = need;
+      found = true;
     }
   }
+  sampler_window(n_points, s, &sp->win_lo, &sp->win_hi, &sp->cand_cap);
   if (!found)
     return set_error(BM_ENOTSUP, "k*d = %d*%d centroids do not fit in one workgroup's LDS", k, d);
   int gmax = 0;
@@ -191,7 +194,7 @@ struct SolverBuffers {
 };
 
 // Lay out every solver buffer; with base == nullptr only the size is computed.
-static void layout_solver(char* base, int64_t s, int d, int k, int T, int cand_cap, bool own_P,
+static void layout_solver(char* base, int64_t s, int d, int k, int T, int64_t cand_cap, bool own_P,
                           bool own_idx, bool own_labels, bool own_inc, int final_grid,
                           SolverBuffers* b) {
   Layout L;
@@ -235,7 +238,7 @@ static void layout_solver(char* base, int64_t s, int d, int k, int T, int cand_c
   b->bytes = L.off + 256;
 }
 
-static bm_status prepare_solver(hipStream_t stream, int64_t s, int d, int k, int T, int cand_cap,
+static bm_status prepare_solver(hipStream_t stream, int64_t s, int d, int k, int T, int64_t cand_cap,
                                 bool own_P, bool own_idx, bool own_labels, bool own_inc,
                                 int final_grid, SolverBuffers* b) {
   SolverArgs keep = b->a;
@@ -357,7 +360,10 @@ bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s
   a.do_keep = 1;
   a.init_incumbent = o.resume ? 0 : 1;
   a.sums_in_lds = sp.sums_in_lds;
+  a.c64_in_lds = sp.c64_in_lds;
   a.cand_cap = sp.cand_cap;
+  a.win_lo = sp.win_lo;
+  a.win_hi = sp.win_hi;
   a.spin_limit = o.spin_limit ? o.spin_limit : kDefaultSpinLimit;
   a.sample_idx_out = o.sample_idx;
 
@@ -503,7 +509,10 @@ static bm_status run_solver_on_sample(const float* P, int64_t s, int32_t d, int3
   a.do_seed = seed_only ? 1 : 0;
   a.do_lloyd = seed_only ? 0 : 1;
   a.sums_in_lds = sp.sums_in_lds;
+  a.c64_in_lds = sp.c64_in_lds;
   a.cand_cap = sp.cand_cap;
+  a.win_lo = sp.win_lo;
+  a.win_hi = sp.win_hi;
   a.spin_limit = o.spin_limit ? o.spin_limit : kDefaultSpinLimit;
   BM_HIP(hipMemcpyAsync(a.deg_inc, deg, size_t(k), hipMemcpyHostToDevice, stream));
   if ((st = launch_solver(a, sp.grid, sp.lds, stream)) != BM_OK) return st;
@@ -578,7 +587,10 @@ bm_status bm_sample_indices(int64_t n, int64_t s, uint64_t seed, int32_t t, int3
   a.trials = 1;
   a.do_sample = 1;
   a.cand_cap = sp.cand_cap;
+  a.win_lo = sp.win_lo;
+  a.win_hi = sp.win_hi;
   a.sums_in_lds = sp.sums_in_lds;
+  a.c64_in_lds = sp.c64_in_lds;
   a.spin_limit = o.spin_limit ? o.spin_limit : kDefaultSpinLimit;
   if ((st = launch_solver(a, sp.grid, sp.lds, stream)) != BM_OK) return st;
   return check_solver_error(a, stream, nullptr);

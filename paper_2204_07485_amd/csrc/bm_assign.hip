@@ -37,10 +37,12 @@ __global__ void __launch_bounds__(kAssignBlock)
     const int t = e - j * DM;
     Cl[e] = (t < d) ? C[static_cast<size_t>(j) * d + t] : 0.f;
   }
-  if (tid == 0) {
+  for (int j = tid; j < k; j += kAssignBlock) act[j] = (deg && deg[j]) ? 1 : 0;
+  __syncthreads();
+  if (tid == 0) {  // compact the active slots in place, ascending
     int na = 0;
     for (int j = 0; j < k; ++j)
-      if (!deg || !deg[j]) act[na++] = j;
+      if (!act[j]) act[na++] = j;
     s_na = na;
   }
   __syncthreads();
@@ -71,13 +73,16 @@ __global__ void __launch_bounds__(kAssignBlock)
     s_last = (prev == gridDim.x - 1) ? 1 : 0;
   }
   __syncthreads();
-  if (s_last && tid == 0) {
+  if (s_last) {  // the last workgroup adds the partials in a fixed order
     __threadfence();
-    double total = 0.0;
-    for (unsigned int b = 0; b < gridDim.x; ++b)
-      total += __hip_atomic_load(&partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *sse_out = total;
-    __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double v = 0.0;
+    for (unsigned int b = tid; b < gridDim.x; b += kAssignBlock)
+      v += __hip_atomic_load(&partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double total = block_sum_f64<kAssignBlock>(v, s_tmp);
+    if (tid == 0) {
+      *sse_out = total;
+      __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 

@@ -14,10 +14,14 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 
 // ---------------------------------------------------------------------------
 // Grid barrier for a cooperative launch (every workgroup is resident).
-// Arrival counter plus generation word; the last arriver resets the counter
-// and publishes the next generation.  A waiter that polls more than
-// spin_limit times raises `abort`, and every later barrier returns false at
-// once, so a logic error ends the kernel instead of hanging it.
+// Arrival counter plus generation word.  Each workgroup publishes its writes
+// with one agent-scope release fence before arriving, polls the generation
+// with relaxed loads (no cache maintenance per poll) and takes one
+// agent-scope acquire fence after the wait; the last arriver acquires all
+// arrivals, resets the counter and publishes the next generation with a
+// release store.  A waiter that polls more than spin_limit times raises `abort`,
+// and every later barrier returns false at once, so a logic error ends the
+// kernel instead of hanging it.
 struct GridBarrier {
   unsigned int arrive;
   unsigned int gen;
@@ -36,15 +40,18 @@ __device__ __forceinline__ bool grid_barrier(GridBarrier* b, unsigned int nblock
     } else {
       const unsigned int g =
           __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const unsigned int prev =
-          __hip_atomic_fetch_add(&b->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(&b->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (prev == nblocks - 1) {
+        // acquire every arrival, reset the counter, then publish the new
+        // generation with a release store (ordered after the reset)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __hip_atomic_store(&b->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&b->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         unsigned int polls = 0;
-        while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
           if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
             ok = 0;
             break;
@@ -56,8 +63,8 @@ __device__ __forceinline__ bool grid_barrier(GridBarrier* b, unsigned int nblock
           }
           __builtin_amdgcn_s_sleep(1);
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
-      __threadfence();
     }
     s_ok = ok;
   }

@@ -55,7 +55,10 @@ struct SolverArgs {
   int32_t do_keep;
   int32_t init_incumbent;
   int32_t sums_in_lds;
-  int32_t cand_cap;          // power of two, <= what the LDS sort buffer holds
+  int32_t c64_in_lds;
+  int64_t cand_cap;          // capacity of the global candidate list
+  uint64_t win_lo;           // predicted key window of the sampler (inclusive)
+  uint64_t win_hi;
   uint32_t spin_limit;
   // sample-sized buffers
   float* P;                  // s x d
@@ -99,7 +102,8 @@ bm_status set_error(bm_status code, const char* fmt, ...);
 void clear_error();
 
 // Launchers (defined in bm_solver.hip / bm_assign.hip).
-size_t solver_lds_bytes(int dm, int k, int d, int grid, int cand_cap, bool sums_in_lds);
+size_t solver_lds_bytes(int dm, int k, int d, bool sums_in_lds, bool c64_in_lds);
+void sampler_window(int64_t n, int64_t s, uint64_t* lo, uint64_t* hi, int64_t* cap);
 int padded_dim(int d);
 bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t stream);
 bm_status solver_max_grid(int dm, size_t lds, int* max_grid);

@@ -38,21 +38,27 @@ struct Lds {
   int* misc;         // [0] number of active slots, [1] chosen bucket, [2] hit flag
   int64_t* misc64;   // [0] bucket count, [1] found row, [2] fallback row, [3] pick
   double* miscd;     // [0] broadcast value, [1..] per-trial scratch
+  double* c64;       // k x d FP64 means (when they fit)
   unsigned char* B;  // phase-local region
 };
 
 __device__ __forceinline__ int64_t imin64(int64_t x, int64_t y) { return x < y ? x : y; }
 
+// Row stride (in doubles) of the per-cluster sums in LDS: odd, so the same
+// coordinate of different clusters falls in different LDS banks.
+__host__ __device__ __forceinline__ int sums_ld(int d) { return (d & 1) ? d : d + 1; }
+
 __host__ __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 struct LdsPlan {
-  size_t C, act, degf, tmpi, tmpd, misc, misc64, miscd, B;
-  size_t hist, skey, sidx, selc, total_sampling;
+  size_t C, act, degf, tmpi, tmpd, misc, misc64, miscd, c64, B;
+  size_t hist, selc, total_sampling;
   size_t sums, cntl, total_lloyd;
   size_t total;
 };
 
-__host__ __device__ inline LdsPlan plan_lds(int dm, int k, int d, int cand_cap, bool sums_in_lds) {
+__host__ __device__ inline LdsPlan plan_lds(int dm, int k, int d, bool sums_in_lds,
+                                            bool c64_in_lds) {
   LdsPlan p;
   size_t o = 0;
   p.C = o; o = align16(o + sizeof(float) * size_t(k) * dm);
@@ -63,15 +69,17 @@ __host__ __device__ inline LdsPlan plan_lds(int dm, int k, int d, int cand_cap, 
   p.misc = o; o = align16(o + sizeof(int) * 8);
   p.misc64 = o; o = align16(o + sizeof(int64_t) * 8);
   p.miscd = o; o = align16(o + sizeof(double) * (4 + 4 * kMaxTrials));
+  p.c64 = o; o = align16(o + (c64_in_lds ? sizeof(double) * size_t(k) * d : 0));
   p.B = o;
   size_t b = 0;
   p.hist = b; b = align16(b + sizeof(unsigned int) * kHistBins);
-  p.skey = b; b = align16(b + sizeof(uint64_t) * size_t(cand_cap));
-  p.sidx = b; b = align16(b + sizeof(int32_t) * size_t(cand_cap));
   p.selc = b; b = align16(b + sizeof(unsigned int) * kMaxGrid);
+  // K-means++: scan staging (kBlock doubles) and the candidate rows
+  const size_t seed_stage = sizeof(double) * kBlock + sizeof(float) * kMaxTrials * size_t(dm);
+  if (b < seed_stage) b = seed_stage;
   p.total_sampling = b;
   b = 0;
-  p.sums = b; b = align16(b + (sums_in_lds ? sizeof(double) * size_t(k) * d : 0));
+  p.sums = b; b = align16(b + (sums_in_lds ? sizeof(double) * size_t(k) * sums_ld(d) : 0));
   p.cntl = b; b = align16(b + sizeof(int) * size_t(k));
   p.total_lloyd = b;
   p.total = o + (p.total_sampling > p.total_lloyd ? p.total_sampling : p.total_lloyd);
@@ -88,6 +96,7 @@ __device__ __forceinline__ Lds carve(unsigned char* base, const LdsPlan& p) {
   L.misc = reinterpret_cast<int*>(base + p.misc);
   L.misc64 = reinterpret_cast<int64_t*>(base + p.misc64);
   L.miscd = reinterpret_cast<double*>(base + p.miscd);
+  L.c64 = reinterpret_cast<double*>(base + p.c64);
   L.B = base + p.B;
   return L;
 }
@@ -103,15 +112,31 @@ __device__ __forceinline__ bool sync_grid(const SolverArgs& a) {
   return ok;
 }
 
-// Rebuild the ascending list of active slots from the flags (whole block).
+// Sum of G per-workgroup partials p[g * stride] (G <= 2 * kBlock), loaded in
+// parallel and combined in a fixed order, so every workgroup gets the same bits.
+__device__ __forceinline__ double grid_partials_sum(const double* p, int G, int stride,
+                                                    double* tmp) {
+  const int g0 = 2 * threadIdx.x;
+  double v = 0.0;
+  if (g0 < G) v = p[static_cast<size_t>(g0) * stride];
+  if (g0 + 1 < G) v += p[static_cast<size_t>(g0 + 1) * stride];
+  return block_sum_f64<kBlock>(v, tmp);
+}
+
+// Rebuild the ascending list of active slots from the flags (whole block):
+// a block-wide exclusive scan of the "active" flags gives each slot its place.
 __device__ __forceinline__ void rebuild_active(Lds& L, int k) {
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int na = 0;
-    for (int j = 0; j < k; ++j)
-      if (!L.degf[j]) L.act[na++] = j;
-    L.misc[0] = na;
+  int base = 0;
+  for (int j0 = 0; j0 < k; j0 += kBlock) {
+    const int j = j0 + threadIdx.x;
+    const int f = (j < k && !L.degf[j]) ? 1 : 0;
+    int tot = 0;
+    const int ex = block_exclusive_scan<kBlock, int>(f, L.tmpi, tot);
+    if (f) L.act[base + ex] = j;
+    base += tot;
   }
+  if (threadIdx.x == 0) L.misc[0] = base;
   __syncthreads();
 }
 
@@ -120,9 +145,6 @@ __device__ __forceinline__ void rebuild_active(Lds& L, int k) {
 
 __device__ __forceinline__ bool key_in_window(uint64_t key, uint64_t pre, int nbits) {
   return nbits == 0 || (key >> (64 - nbits)) == pre;
-}
-__device__ __forceinline__ bool key_below_window(uint64_t key, uint64_t pre, int nbits) {
-  return nbits != 0 && (key >> (64 - nbits)) < pre;
 }
 __device__ __forceinline__ bool pair_le(uint64_t k, int64_t i, uint64_t tk, int64_t ti) {
   return k < tk || (k == tk && i <= ti);
@@ -168,77 +190,139 @@ __device__ __forceinline__ void emit_point(const SolverArgs& a, int tt, int64_t 
   }
 }
 
-// WG 0: sort the collected window, fix the threshold pair and the output
-// offset of every workgroup.
-__device__ bool select_threshold(const SolverArgs& a, const LdsPlan& pl, Lds& L, int64_t below,
+// WG 0: the need-th smallest (key, index) pair among the m collected
+// candidates (exact MSB radix select over 8-bit digits, candidates read from
+// global memory), then the output offset of every workgroup.  Every key below
+// the window is selected, so workgroup g emits wg_lo[g] plus its candidates
+// that do not exceed the threshold pair.
+__device__ __forceinline__ bool select_threshold(const SolverArgs& a, const LdsPlan& pl, Lds& L, int64_t below,
                                  int64_t m, int64_t ppw) {
   const int tid = threadIdx.x;
   const int G = gridDim.x;
-  uint64_t* skey = reinterpret_cast<uint64_t*>(L.B + pl.skey);
-  int32_t* sidx = reinterpret_cast<int32_t*>(L.B + pl.sidx);
+  unsigned int* hist = reinterpret_cast<unsigned int*>(L.B + pl.hist);
   unsigned int* selc = reinterpret_cast<unsigned int*>(L.B + pl.selc);
-
-  const unsigned int got = __hip_atomic_load(a.cand_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const int64_t need = a.s - below;
-  if (static_cast<int64_t>(got) != m || m > a.cand_cap || need < 1 || need > m) {
+  if (m > a.cand_cap || need < 1 || need > m) {
     if (tid == 0) set_err(a, kErrSelect);
     return false;
   }
-  int n2 = 2;
-  while (n2 < m) n2 <<= 1;
-  for (int r = tid; r < n2; r += kBlock) {
-    if (r < m) {
-      skey[r] = a.cand_key[r];
-      sidx[r] = a.cand_idx[r];
-    } else {
-      skey[r] = ~0ull;
-      sidx[r] = 0x7fffffff;
+  uint64_t pre = 0;
+  int nbits = 0;
+  int64_t rem = need;  // rank inside the current prefix class
+  int64_t cnt = m;
+  while (cnt > 1 && nbits < 64) {
+    for (int b = tid; b < kHistBins; b += kBlock) hist[b] = 0u;
+    __syncthreads();
+    const int shift = 56 - nbits;
+    for (int64_t r = tid; r < m; r += kBlock) {
+      const uint64_t key = a.cand_key[r];
+      if (key_in_window(key, pre, nbits)) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) L.misc[1] = -1;
+    const int hb = (tid < kHistBins) ? static_cast<int>(hist[tid]) : 0;
+    int tot = 0;
+    const int ex = block_exclusive_scan<kBlock, int>(hb, L.tmpi, tot);
+    if (tid < kHistBins && ex < rem && rem <= static_cast<int64_t>(ex) + hb) {
+      L.misc[1] = tid;
+      L.misc64[0] = ex;
+      L.misc64[1] = hb;
+    }
+    __syncthreads();
+    if (L.misc[1] < 0) {
+      if (tid == 0) set_err(a, kErrSelect);
+      return false;
+    }
+    rem -= L.misc64[0];
+    pre = (pre << 8) | static_cast<uint64_t>(L.misc[1]);
+    nbits += 8;
+    cnt = L.misc64[1];
+    __syncthreads();
+  }
+  // the threshold is the rem-th smallest index among the candidates whose
+  // key has prefix `pre` (one candidate, or equal 64-bit keys)
+  if (tid == 0) L.misc64[2] = -1;
+  __syncthreads();
+  for (int64_t r = tid; r < m; r += kBlock) {
+    const uint64_t key = a.cand_key[r];
+    if (!key_in_window(key, pre, nbits)) continue;
+    const int32_t idx = a.cand_idx[r];
+    int64_t rank = 0;
+    if (cnt > 1) {
+      for (int64_t r2 = 0; r2 < m; ++r2)
+        if (key_in_window(a.cand_key[r2], pre, nbits) && a.cand_idx[r2] < idx) ++rank;
+    }
+    if (rank == rem - 1) {
+      L.misc64[2] = idx;
+      L.misc64[3] = static_cast<int64_t>(key);
     }
   }
   for (int gg = tid; gg < G; gg += kBlock) selc[gg] = 0u;
   __syncthreads();
-  // bitonic sort by (key, index), ascending
-  for (int kk = 2; kk <= n2; kk <<= 1) {
-    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-      for (int r = tid; r < n2; r += kBlock) {
-        const int partner = r ^ jj;
-        if (partner > r) {
-          const bool up = (r & kk) == 0;
-          const uint64_t ka = skey[r], kb = skey[partner];
-          const int32_t ia = sidx[r], ib = sidx[partner];
-          const bool a_gt_b = ka > kb || (ka == kb && ia > ib);
-          if (a_gt_b == up) {
-            skey[r] = kb; skey[partner] = ka;
-            sidx[r] = ib; sidx[partner] = ia;
-          }
-        }
-      }
-      __syncthreads();
-    }
+  if (L.misc64[2] < 0) {
+    if (tid == 0) set_err(a, kErrSelect);
+    return false;
   }
-  for (int64_t r = tid; r < need; r += kBlock) {
-    const int64_t i = sidx[r];
-    const int owner = static_cast<int>((i >> 1) / ppw);
-    atomicAdd(&selc[owner], 1u);
+  const uint64_t tk = static_cast<uint64_t>(L.misc64[3]);
+  const int64_t ti = L.misc64[2];
+  for (int64_t r = tid; r < m; r += kBlock) {
+    const uint64_t key = a.cand_key[r];
+    const int64_t idx = a.cand_idx[r];
+    if (pair_le(key, idx, tk, ti)) atomicAdd(&selc[static_cast<int>((idx >> 1) / ppw)], 1u);
   }
   __syncthreads();
+  // output offset of every workgroup: exclusive scan of (selected candidates
+  // + keys below the window), two workgroups per thread
+  for (int gg = tid; gg < G; gg += kBlock) selc[gg] += a.wg_lo[gg];
+  __syncthreads();
+  const int g0 = 2 * tid;
+  const int v0 = (g0 < G) ? static_cast<int>(selc[g0]) : 0;
+  const int v1 = (g0 + 1 < G) ? static_cast<int>(selc[g0 + 1]) : 0;
+  int total = 0;
+  const int ex = block_exclusive_scan<kBlock, int>(v0 + v1, L.tmpi, total);
+  if (g0 < G) a.wg_off[g0] = static_cast<uint32_t>(ex);
+  if (g0 + 1 < G) a.wg_off[g0 + 1] = static_cast<uint32_t>(ex + v0);
   if (tid == 0) {
-    a.thr[0] = skey[need - 1];
-    a.thr[1] = static_cast<uint64_t>(sidx[need - 1]);
-    int64_t run = 0;
-    for (int gg = 0; gg < G; ++gg) {
-      a.wg_off[gg] = static_cast<uint32_t>(run);
-      run += static_cast<int64_t>(selc[gg]) + a.wg_lo[gg];
-    }
-    __hip_atomic_store(a.cand_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (run != a.s) set_err(a, kErrSelect);
-    L.misc[2] = (run == a.s) ? 1 : 0;
+    a.thr[0] = tk;
+    a.thr[1] = static_cast<uint64_t>(ti);
+    if (total != a.s) set_err(a, kErrSelect);
+    L.misc[2] = (total == a.s) ? 1 : 0;
   }
   __syncthreads();
   return L.misc[2] != 0;
 }
 
-__device__ bool sample_phase(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint32_t t, int tt,
+// Collect pass over this workgroup's point pairs: count the keys below
+// [lo, hi] (inclusive) into wg_lo[g] and append the keys inside to the
+// candidate list.
+__device__ __forceinline__ void collect_pass(const SolverArgs& a, Lds& L, uint32_t t, int64_t p0, int64_t p1,
+                             uint64_t lo, uint64_t hi) {
+  const int tid = threadIdx.x;
+  const int64_t n = a.n;
+  int lo_count = 0;
+  const int64_t tiles = (p1 - p0 + kBlock - 1) / kBlock;
+  for (int64_t tile = 0; tile < tiles; ++tile) {
+    const int64_t p = p0 + tile * kBlock + tid;
+    const bool v0 = p < p1;
+    const bool v1 = v0 && (2 * p + 1 < n);
+    uint64_t k0 = 0, k1 = 0;
+    if (v0) sample_key_pair(a.seed, t, static_cast<uint64_t>(p), k0, k1);
+    lo_count += (v0 && k0 < lo) ? 1 : 0;
+    lo_count += (v1 && k1 < lo) ? 1 : 0;
+    append_candidate(a, v0 && k0 >= lo && k0 <= hi, k0, 2 * p);
+    append_candidate(a, v1 && k1 >= lo && k1 <= hi, k1, 2 * p + 1);
+  }
+  const int wg_lo = block_sum_i32<kBlock>(lo_count, L.tmpi);
+  if (tid == 0) a.wg_lo[blockIdx.x] = static_cast<uint32_t>(wg_lo);
+}
+
+// Sample t: the s smallest (key, index) pairs, emitted in index order with
+// their rows gathered into P.  The key window [win_lo, win_hi] predicted from
+// the order statistics of uniform keys (the s-th smallest of n lies within
+// 8 standard deviations of s/n of the key range, plus a margin) almost always
+// holds the threshold, so one collect pass suffices; otherwise MSB histogram
+// passes narrow an exact window first.
+__device__ __forceinline__ bool sample_phase(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint32_t t, int tt,
                              int64_t& hist_passes) {
   const int tid = threadIdx.x;
   const int g = blockIdx.x;
@@ -250,86 +334,97 @@ __device__ bool sample_phase(const SolverArgs& a, const LdsPlan& pl, Lds& L, uin
   const int64_t p1 = imin64(npairs, p0 + ppw);
   unsigned int* hist = reinterpret_cast<unsigned int*>(L.B + pl.hist);
 
-  uint64_t pre = 0;
-  int nbits = 0;
-  int64_t below = 0;
-  int64_t m = n;
-  while (m > a.cand_cap) {
-    if (nbits >= 64) {
-      if (tid == 0) set_err(a, kErrSelect);
-      return false;
-    }
-    unsigned int* Hcur = a.hist + (hist_passes % 3) * kHistBins;
-    unsigned int* Hnext = a.hist + ((hist_passes + 1) % 3) * kHistBins;
-    for (int b = tid; b < kHistBins; b += kBlock) hist[b] = 0u;
-    if (g == 0)
-      for (int b = tid; b < kHistBins; b += kBlock) Hnext[b] = 0u;
-    __syncthreads();
-    const int shift = 56 - nbits;
-    for (int64_t p = p0 + tid; p < p1; p += kBlock) {
-      uint64_t k0, k1;
-      sample_key_pair(a.seed, t, static_cast<uint64_t>(p), k0, k1);
-      if (key_in_window(k0, pre, nbits)) atomicAdd(&hist[(k0 >> shift) & 255u], 1u);
-      if (2 * p + 1 < n && key_in_window(k1, pre, nbits))
-        atomicAdd(&hist[(k1 >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    for (int b = tid; b < kHistBins; b += kBlock) {
-      const unsigned int v = hist[b];
-      if (v) atomicAdd(&Hcur[b], v);
+  // fast path: predicted window
+  collect_pass(a, L, t, p0, p1, a.win_lo, a.win_hi);
+  if (!sync_grid(a)) return false;
+  {
+    const int g0 = 2 * tid;
+    int v = 0;
+    if (g0 < G) v += static_cast<int>(a.wg_lo[g0]);
+    if (g0 + 1 < G) v += static_cast<int>(a.wg_lo[g0 + 1]);
+    const int64_t below = block_sum_i32<kBlock>(v, L.tmpi);
+    const int64_t m = __hip_atomic_load(a.cand_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool hit = m <= a.cand_cap && below < a.s && a.s <= below + m;
+    if (g == 0) {
+      if (hit && !select_threshold(a, pl, L, below, m, ppw)) return false;
+      if (tid == 0) __hip_atomic_store(a.cand_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (!sync_grid(a)) return false;
-    if (tid == 0) {
-      const int64_t need = a.s - below;
-      int64_t cum = 0;
-      int b = 0;
-      for (; b < kHistBins; ++b) {
-        const int64_t h = Hcur[b];
-        if (cum + h >= need) break;
-        cum += h;
+    if (!hit) {
+      // exact fallback: histogram passes over the key prefixes
+      uint64_t pre = 0;
+      int nbits = 0;
+      int64_t blw = 0;
+      int64_t mm = n;
+      while (mm > a.cand_cap) {
+        if (nbits >= 64) {
+          if (tid == 0) set_err(a, kErrSelect);
+          return false;
+        }
+        unsigned int* Hcur = a.hist + (hist_passes % 3) * kHistBins;
+        unsigned int* Hnext = a.hist + ((hist_passes + 1) % 3) * kHistBins;
+        for (int b = tid; b < kHistBins; b += kBlock) hist[b] = 0u;
+        if (g == 0)
+          for (int b = tid; b < kHistBins; b += kBlock) Hnext[b] = 0u;
+        __syncthreads();
+        const int shift = 56 - nbits;
+        for (int64_t p = p0 + tid; p < p1; p += kBlock) {
+          uint64_t k0, k1;
+          sample_key_pair(a.seed, t, static_cast<uint64_t>(p), k0, k1);
+          if (key_in_window(k0, pre, nbits)) atomicAdd(&hist[(k0 >> shift) & 255u], 1u);
+          if (2 * p + 1 < n && key_in_window(k1, pre, nbits))
+            atomicAdd(&hist[(k1 >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        for (int b = tid; b < kHistBins; b += kBlock) {
+          const unsigned int v2 = hist[b];
+          if (v2) atomicAdd(&Hcur[b], v2);
+        }
+        if (!sync_grid(a)) return false;
+        const int64_t need = a.s - blw;
+        if (tid == 0) L.misc[1] = -1;
+        const int hb = (tid < kHistBins) ? static_cast<int>(Hcur[tid]) : 0;
+        int tot = 0;
+        const int ex = block_exclusive_scan<kBlock, int>(hb, L.tmpi, tot);
+        if (tid < kHistBins && ex < need && need <= static_cast<int64_t>(ex) + hb) {
+          L.misc[1] = tid;
+          L.misc64[0] = ex;
+          L.misc64[1] = hb;
+        }
+        __syncthreads();
+        if (L.misc[1] < 0) {
+          if (tid == 0) set_err(a, kErrSelect);
+          return false;
+        }
+        blw += L.misc64[0];
+        pre = (pre << 8) | static_cast<uint64_t>(L.misc[1]);
+        nbits += 8;
+        mm = L.misc64[1];
+        ++hist_passes;
+        __syncthreads();
       }
-      if (b == kHistBins) b = kHistBins - 1;  // inconsistent counts; caught below
-      L.misc[1] = b;
-      L.misc64[0] = cum;
-      L.misc64[1] = Hcur[b];
+      const uint64_t lo = nbits ? pre << (64 - nbits) : 0ull;
+      const uint64_t hi = nbits ? lo | (~0ull >> nbits) : ~0ull;
+      collect_pass(a, L, t, p0, p1, lo, hi);
+      if (!sync_grid(a)) return false;
+      if (g == 0) {
+        const int64_t got = __hip_atomic_load(a.cand_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (got != mm) {
+          if (tid == 0) set_err(a, kErrSelect);
+          return false;
+        }
+        if (!select_threshold(a, pl, L, blw, mm, ppw)) return false;
+        if (tid == 0) __hip_atomic_store(a.cand_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (!sync_grid(a)) return false;
     }
-    __syncthreads();
-    below += L.misc64[0];
-    pre = (pre << 8) | static_cast<uint64_t>(L.misc[1]);
-    nbits += 8;
-    m = L.misc64[1];
-    ++hist_passes;
-    __syncthreads();
   }
-
-  // collect the window; count keys below it
-  int lo_count = 0;
-  const int64_t span = p1 - p0;
-  const int64_t tiles = (span + kBlock - 1) / kBlock;
-  for (int64_t tile = 0; tile < tiles; ++tile) {
-    const int64_t p = p0 + tile * kBlock + tid;
-    const bool v0 = p < p1;
-    const bool v1 = v0 && (2 * p + 1 < n);
-    uint64_t k0 = 0, k1 = 0;
-    if (v0) sample_key_pair(a.seed, t, static_cast<uint64_t>(p), k0, k1);
-    lo_count += (v0 && key_below_window(k0, pre, nbits)) ? 1 : 0;
-    lo_count += (v1 && key_below_window(k1, pre, nbits)) ? 1 : 0;
-    append_candidate(a, v0 && key_in_window(k0, pre, nbits), k0, 2 * p);
-    append_candidate(a, v1 && key_in_window(k1, pre, nbits), k1, 2 * p + 1);
-  }
-  const int wg_lo = block_sum_i32<kBlock>(lo_count, L.tmpi);
-  if (tid == 0) a.wg_lo[g] = static_cast<uint32_t>(wg_lo);
-  if (!sync_grid(a)) return false;
-
-  if (g == 0) {
-    if (!select_threshold(a, pl, L, below, m, ppw)) return false;
-  }
-  if (!sync_grid(a)) return false;
 
   // emit in index order and gather
   const uint64_t tk = a.thr[0];
   const int64_t ti = static_cast<int64_t>(a.thr[1]);
   int64_t base = a.wg_off[g];
+  const int64_t tiles = (p1 - p0 + kBlock - 1) / kBlock;
   for (int64_t tile = 0; tile < tiles; ++tile) {
     const int64_t p = p0 + tile * kBlock + tid;
     const bool v0 = p < p1;
@@ -348,12 +443,27 @@ __device__ bool sample_phase(const SolverArgs& a, const LdsPlan& pl, Lds& L, uin
   return sync_grid(a);
 }
 
+// Sample rows a thread keeps in registers across Lloyd rounds (rows
+// r0 + tid + q * kBlock), used when the workgroup's chunk fits: every grid
+// barrier ends with an acquire fence that drops the L2's copy of the sample,
+// so re-reading it would cost a memory round trip per round.
+template <int DM>
+struct RowCache {
+  static constexpr int kRows = DM <= 16 ? 1 : 0;
+  float x[kRows > 0 ? kRows : 1][DM];
+};
+
 // ---------------------------------------------------------------------------
 // 2. K-means++ reseeding of the degenerate slots.
+//
+// The D^2 weights are FP64 direct differences of the FP32 values, formed in
+// dimension order with FMAs, so they are the same numbers the FP64 definition
+// gives.  The running sum that inverts a draw is taken over workgroup chunks
+// (a fixed-order scan of per-workgroup sums) and then inside the owning chunk.
 
 template <int DM>
-__device__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32_t t, int64_t r0, int64_t r1,
-                             int64_t& nd, int64_t& nres, int64_t& nbound) {
+__device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32_t t, int64_t r0, int64_t r1,
+                             bool cached, const RowCache<DM>& rc, int64_t& nd, int64_t& nres) {
   const int tid = threadIdx.x;
   const int g = blockIdx.x;
   const int G = gridDim.x;
@@ -365,18 +475,39 @@ __device__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32_t t, int64_t r0
   double* tgt = L.miscd + 4;                 // per-trial target
   double* basev = L.miscd + 4 + kMaxTrials;  // per-trial chunk base
   int* owner = L.tmpi + 16;                  // per-trial owning workgroup (tmpi has 32)
+  double* incl_l = reinterpret_cast<double*>(L.B);                            // kBlock doubles
+  float* cand_rows = reinterpret_cast<float*>(L.B + sizeof(double) * kBlock);  // trials x DM
+  const int64_t tiles = (r1 - r0 + kBlock - 1) / kBlock;
+  // with cached rows the chunk is a single tile and the weight stays in a register
+  double w_reg = 0.0;
+  auto row = [&](int64_t tile, float (&x)[DM]) {
+    if (cached) {
+#pragma unroll
+      for (int tdim = 0; tdim < DM; ++tdim) x[tdim] = rc.x[0][tdim];
+    } else {
+      load_row_f32<DM>(a.P + static_cast<size_t>(r0 + tile * kBlock + tid) * d, d, x);
+    }
+  };
+  auto get_w = [&](int64_t tile, int64_t i) { return cached ? w_reg : a.w[i]; };
+  auto set_w = [&](int64_t i, double v) {
+    if (cached) w_reg = v;
+    else a.w[i] = v;
+  };
 
   if (L.misc[0] > 0) {
     const int na = L.misc[0];
     double part = 0.0;
-    for (int64_t i = r0 + tid; i < r1; i += kBlock) {
-      const float* p = a.P + static_cast<size_t>(i) * d;
+    for (int64_t tile = 0; tile < tiles; ++tile) {
+      const int64_t i = r0 + tile * kBlock + tid;
+      if (i >= r1) continue;
+      float x[DM];
+      row(tile, x);
       double best = __builtin_inf();
       for (int aa = 0; aa < na; ++aa) {
-        const double dd = dist2_f64(p, L.C + L.act[aa] * DM, d);
+        const double dd = dist2_f64_row<DM>(x, L.C + L.act[aa] * DM);
         if (dd < best) best = dd;
       }
-      a.w[i] = best;
+      set_w(i, best);
       part += best;
     }
     const double ws = block_sum_f64<kBlock>(part, L.tmpd);
@@ -393,34 +524,41 @@ __device__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32_t t, int64_t r0
       pick = static_cast<int64_t>(below_from_word(seed_draw(a.seed, t, q), static_cast<uint64_t>(s)));
       ++q;
     } else {
-      if (tid == 0) {
-        double W = 0.0;
-        for (int gg = 0; gg < G; ++gg) W += a.wsum[gg];
-        L.miscd[0] = W;
+      // W and, per draw, the chunk holding the target: inclusive scan of the
+      // per-workgroup weight sums (two chunks per thread, fixed order); chunk g
+      // starts at E_g, the scan value before it
+      {
+        const int g0 = 2 * tid;
+        const double w0 = (g0 < G) ? a.wsum[g0] : 0.0;
+        const double w1 = (g0 + 1 < G) ? a.wsum[g0 + 1] : 0.0;
+        double tot = 0.0;
+        const double incl = block_inclusive_scan_f64<kBlock>(w0 + w1, L.tmpd, tot);
+        incl_l[tid] = incl;
+        if (tid < kMaxTrials) { owner[tid] = 0x7fffffff; L.tmpi[24 + tid] = -1; }
+        __syncthreads();
+        const double e0 = tid > 0 ? incl_l[tid - 1] : 0.0;
+        const double e1 = e0 + w0;
         for (int l = 0; l < trials; ++l) {
-          const double target = unit_from_word(seed_draw(a.seed, t, q + l)) * W;
-          double E = 0.0;
-          int own = -1;
-          for (int gg = 0; gg < G; ++gg) {
-            const double wsg = a.wsum[gg];
-            if (E + wsg > target) { own = gg; break; }
-            E += wsg;
-          }
-          if (own < 0) {  // rounding: fall back to the last chunk with weight
-            E = 0.0;
-            double Elast = 0.0;
-            for (int gg = 0; gg < G; ++gg) {
-              if (a.wsum[gg] > 0.0) { own = gg; Elast = E; }
-              E += a.wsum[gg];
-            }
-            E = Elast;
-          }
-          tgt[l] = target;
-          basev[l] = E;
-          owner[l] = own;
+          const double target = unit_from_word(seed_draw(a.seed, t, q + l)) * tot;
+          if (g0 < G && e0 + w0 > target) atomicMin(&owner[l], g0);
+          else if (g0 + 1 < G && e1 + w1 > target) atomicMin(&owner[l], g0 + 1);
+          if (g0 < G && w0 > 0.0) atomicMax(&L.tmpi[24 + l], g0);      // last chunk with weight
+          if (g0 + 1 < G && w1 > 0.0) atomicMax(&L.tmpi[24 + l], g0 + 1);
+          if (tid == 0) tgt[l] = target;
         }
+        __syncthreads();
+        if (tid == 0) {
+          for (int l = 0; l < trials; ++l)
+            if (owner[l] == 0x7fffffff) owner[l] = L.tmpi[24 + l];  // rounding fallback
+        }
+        __syncthreads();
+        for (int l = 0; l < trials; ++l) {
+          if (g0 == owner[l]) basev[l] = e0;
+          if (g0 + 1 == owner[l]) basev[l] = e1;
+        }
+        if (tid == 0) L.miscd[0] = tot;
+        __syncthreads();
       }
-      __syncthreads();
       const double W = L.miscd[0];
       if (W == 0.0) break;  // every remaining D^2 is zero: leave the slots degenerate
       q += trials;
@@ -428,12 +566,11 @@ __device__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32_t t, int64_t r0
         if (owner[l] != g) continue;
         const double target = tgt[l];
         double run = basev[l];
-        if (tid == 0) { L.misc64[1] = -1; L.misc64[2] = -1; }
+        if (tid == 0) { L.misc64[1] = -1; L.misc64[3] = 0; }
         __syncthreads();
-        const int64_t tiles = (r1 - r0 + kBlock - 1) / kBlock;
         for (int64_t tile = 0; tile < tiles; ++tile) {
           const int64_t i = r0 + tile * kBlock + tid;
-          const double wi = (i < r1) ? a.w[i] : 0.0;
+          const double wi = (i < r1) ? get_w(tile, i) : 0.0;
           double tot = 0.0;
           const double incl = block_inclusive_scan_f64<kBlock>(wi, L.tmpd, tot);
           const double v = run + incl;
@@ -460,8 +597,10 @@ __device__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32_t t, int64_t r0
           // rounding left the target beyond this chunk: last row with weight
           if (tid == 0) L.misc[2] = -1;
           __syncthreads();
-          for (int64_t i = r0 + tid; i < r1; i += kBlock)
-            if (a.w[i] > 0.0) atomicMax(&L.misc[2], static_cast<int>(i - r0));
+          for (int64_t tile = 0; tile < tiles; ++tile) {
+            const int64_t i = r0 + tile * kBlock + tid;
+            if (i < r1 && get_w(tile, i) > 0.0) atomicMax(&L.misc[2], static_cast<int>(i - r0));
+          }
           __syncthreads();
           if (tid == 0) {
             L.misc64[1] = (L.misc[2] >= 0) ? r0 + L.misc[2] : -1;
@@ -477,29 +616,44 @@ __device__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32_t t, int64_t r0
         __syncthreads();
       }
       if (!sync_grid(a)) return false;
-      if (trials == 1) {
-        pick = a.cand[0];
-      } else {
-        int64_t cands[kMaxTrials];
-        double ph[kMaxTrials];
-        bool valid = true;
+      int64_t cands[kMaxTrials];
+      bool valid = true;
 #pragma unroll
-        for (int l = 0; l < kMaxTrials; ++l) {
-          cands[l] = (l < trials) ? a.cand[l] : 0;
-          valid = valid && cands[l] >= 0 && cands[l] < s;
-          ph[l] = 0.0;
+      for (int l = 0; l < kMaxTrials; ++l) {
+        cands[l] = (l < trials) ? a.cand[l] : 0;
+        valid = valid && cands[l] >= 0 && cands[l] < s;
+      }
+      if (!valid) {
+        if (tid == 0) set_err(a, kErrSeed);
+        return false;
+      }
+      if (trials == 1) {
+        pick = cands[0];
+      } else {
+        // candidate rows into LDS, then the potentials sum_i min(D_i^2, |p_i - c|^2)
+        for (int e = tid; e < trials * DM; e += kBlock) {
+          const int l = e / DM;
+          const int tdim = e - l * DM;
+          int64_t c = cands[0];
+#pragma unroll
+          for (int l2 = 1; l2 < kMaxTrials; ++l2)
+            if (l2 == l) c = cands[l2];
+          cand_rows[e] = (tdim < d) ? a.P[static_cast<size_t>(c) * d + tdim] : 0.f;
         }
-        if (!valid) {
-          if (tid == 0) set_err(a, kErrSeed);
-          return false;
-        }
-        for (int64_t i = r0 + tid; i < r1; i += kBlock) {
-          const float* p = a.P + static_cast<size_t>(i) * d;
-          const double wi = a.w[i];
+        __syncthreads();
+        double ph[kMaxTrials];
+#pragma unroll
+        for (int l = 0; l < kMaxTrials; ++l) ph[l] = 0.0;
+        for (int64_t tile = 0; tile < tiles; ++tile) {
+          const int64_t i = r0 + tile * kBlock + tid;
+          if (i >= r1) continue;
+          float x[DM];
+          row(tile, x);
+          const double wi = get_w(tile, i);
 #pragma unroll
           for (int l = 0; l < kMaxTrials; ++l) {
             if (l < trials) {
-              const double dd = dist2_f64(p, a.P + static_cast<size_t>(cands[l]) * d, d);
+              const double dd = dist2_f64_row<DM>(x, cand_rows + l * DM);
               ph[l] += dd < wi ? dd : wi;
             }
           }
@@ -513,18 +667,16 @@ __device__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32_t t, int64_t r0
         }
         nd += s * trials;
         if (!sync_grid(a)) return false;
-        if (tid == 0) {
-          int best = 0;
-          double best_phi = __builtin_inf();
-          for (int l = 0; l < trials; ++l) {
-            double phi = 0.0;
-            for (int gg = 0; gg < G; ++gg) phi += a.phi_part[gg * kMaxTrials + l];
-            if (phi < best_phi) { best_phi = phi; best = l; }
-          }
-          L.misc64[4] = a.cand[best];
+        int best = 0;
+        double best_phi = __builtin_inf();
+        for (int l = 0; l < trials; ++l) {
+          const double phi = grid_partials_sum(a.phi_part + l, G, kMaxTrials, L.tmpd);
+          if (phi < best_phi) { best_phi = phi; best = l; }
         }
-        __syncthreads();
-        pick = L.misc64[4];
+        pick = cands[0];
+#pragma unroll
+        for (int l = 1; l < kMaxTrials; ++l)
+          if (l == best) pick = cands[l];
       }
     }
     if (pick < 0 || pick >= s) {  // no valid candidate: stop (error already raised)
@@ -539,10 +691,15 @@ __device__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32_t t, int64_t r0
     // update D^2 over this workgroup's rows
     double part = 0.0;
     const float* cj = L.C + j * DM;
-    for (int64_t i = r0 + tid; i < r1; i += kBlock) {
-      const double dd = dist2_f64(a.P + static_cast<size_t>(i) * d, cj, d);
-      const double wi = (na == 0) ? dd : (dd < a.w[i] ? dd : a.w[i]);
-      a.w[i] = wi;
+    for (int64_t tile = 0; tile < tiles; ++tile) {
+      const int64_t i = r0 + tile * kBlock + tid;
+      if (i >= r1) continue;
+      float x[DM];
+      row(tile, x);
+      const double dd = dist2_f64_row<DM>(x, cj);
+      const double wold = get_w(tile, i);
+      const double wi = (na == 0) ? dd : (dd < wold ? dd : wold);
+      set_w(i, wi);
       part += wi;
     }
     const double ws = block_sum_f64<kBlock>(part, L.tmpd);
@@ -552,22 +709,39 @@ __device__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32_t t, int64_t r0
     rebuild_active(L, k);
     if (!sync_grid(a)) return false;
   }
-  (void)nbound;
   return true;
 }
 
 // ---------------------------------------------------------------------------
 // 3. K-means on the sample.
 
-// One assignment pass over this workgroup's rows, optionally accumulating the
-// cluster sums and counts into sums ring slot (pass % 3); ends with a grid
-// barrier and returns the objective of the current centroids on P.
 template <int DM>
-__device__ bool assign_pass(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint32_t pass,
-                            int64_t r0, int64_t r1, bool accumulate, double& f_out) {
+__device__ __forceinline__ void assign_row(const SolverArgs& a, Lds& L, const float (&x)[DM],
+                                           int64_t i, int na, bool accumulate, double* sums_dst,
+                                           int ld, int* cnt_l, double& sse) {
+  int bj;
+  float bd;
+  nearest_f32<DM>(x, L.C, L.act, na, bj, bd);
+  a.labels[i] = bj;
+  sse += dist2_f64_row<DM>(x, L.C + bj * DM);
+  if (accumulate) {
+    atomicAdd(&cnt_l[bj], 1);
+    double* dst = sums_dst + bj * ld;
+#pragma unroll
+    for (int tdim = 0; tdim < DM; ++tdim)
+      if (tdim < a.d) unsafeAtomicAdd(dst + tdim, static_cast<double>(x[tdim]));
+  }
+}
+
+// One assignment pass over this workgroup's rows, optionally accumulating the
+// cluster sums and counts into ring slot (pass % 3).  Ends with a grid
+// barrier; the per-workgroup objectives are left in sse_part[pass % 2].
+template <int DM>
+__device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint32_t pass,
+                            int64_t r0, int64_t r1, bool accumulate, bool cached,
+                            const RowCache<DM>& rc) {
   const int tid = threadIdx.x;
   const int g = blockIdx.x;
-  const int G = gridDim.x;
   const int d = a.d;
   const int k = a.k;
   const int kd = k * d;
@@ -583,83 +757,130 @@ __device__ bool assign_pass(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint
     for (int e = tid; e < kd; e += kBlock) nring[e] = 0.0;
     for (int j = tid; j < k; j += kBlock) ncring[j] = 0;
   }
+  const int ld = a.sums_in_lds ? sums_ld(d) : d;
   if (accumulate) {
     if (a.sums_in_lds)
-      for (int e = tid; e < kd; e += kBlock) sums_l[e] = 0.0;
+      for (int e = tid; e < k * ld; e += kBlock) sums_l[e] = 0.0;
     for (int j = tid; j < k; j += kBlock) cnt_l[j] = 0;
     __syncthreads();
   }
+  double* sums_dst = a.sums_in_lds ? sums_l : ring;
   double sse = 0.0;
-  for (int64_t i = r0 + tid; i < r1; i += kBlock) {
-    float x[DM];
-    load_row_f32<DM>(a.P + static_cast<size_t>(i) * d, d, x);
-    int bj;
-    float bd;
-    nearest_f32<DM>(x, L.C, L.act, na, bj, bd);
-    a.labels[i] = bj;
-    sse += dist2_f64_row<DM>(x, L.C + bj * DM);
-    if (accumulate) {
-      atomicAdd(&cnt_l[bj], 1);
-      double* dst = a.sums_in_lds ? sums_l + bj * d : ring + bj * d;
+  if (cached) {
 #pragma unroll
-      for (int tdim = 0; tdim < DM; ++tdim)
-        if (tdim < d) unsafeAtomicAdd(dst + tdim, static_cast<double>(x[tdim]));
+    for (int q = 0; q < RowCache<DM>::kRows; ++q) {
+      const int64_t i = r0 + tid + static_cast<int64_t>(q) * kBlock;
+      if (i < r1) assign_row<DM>(a, L, rc.x[q], i, na, accumulate, sums_dst, ld, cnt_l, sse);
+    }
+  } else {
+    for (int64_t i = r0 + tid; i < r1; i += kBlock) {
+      float x[DM];
+      load_row_f32<DM>(a.P + static_cast<size_t>(i) * d, d, x);
+      assign_row<DM>(a, L, x, i, na, accumulate, sums_dst, ld, cnt_l, sse);
     }
   }
   const double wsse = block_sum_f64<kBlock>(sse, L.tmpd);
   if (accumulate) {
     if (a.sums_in_lds) {
-      for (int e = tid; e < kd; e += kBlock)
-        if (cnt_l[e / d]) unsafeAtomicAdd(&ring[e], sums_l[e]);
+      for (int e = tid; e < kd; e += kBlock) {
+        const int j = e / d;
+        if (cnt_l[j]) unsafeAtomicAdd(&ring[e], sums_l[j * ld + (e - j * d)]);
+      }
     }
     for (int j = tid; j < k; j += kBlock)
       if (cnt_l[j]) atomicAdd(&cring[j], cnt_l[j]);
   }
   if (tid == 0) a.sse_part[(pass & 1u) * kMaxGrid + g] = wsse;
-  if (!sync_grid(a)) return false;
-  if (tid == 0) {
-    double f = 0.0;
-    for (int gg = 0; gg < G; ++gg) f += a.sse_part[(pass & 1u) * kMaxGrid + gg];
-    L.miscd[0] = f;
-  }
-  __syncthreads();
-  f_out = L.miscd[0];
-  __syncthreads();
-  return true;
+  return sync_grid(a);
 }
 
-// New centroids from ring slot `used`: the mean of each non-empty cluster
-// as an FP64 sum / count (kept in c64, rounded to FP32 for the distance
+// After the barrier of pass `used`: read the objective partials, the cluster
+// sums and the counts in one round of loads (sums staged in the idle LDS sums
+// area when it exists), then return the objective of the pass.
+__device__ __forceinline__ double gather_pass(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint32_t used) {
+  const int tid = threadIdx.x;
+  const int k = a.k;
+  const int kd = k * a.d;
+  const int G = gridDim.x;
+  const double* part = a.sse_part + (used & 1u) * kMaxGrid;
+  const int g0 = 2 * tid;
+  double v = 0.0;
+  if (g0 < G) v = part[g0];
+  if (g0 + 1 < G) v += part[g0 + 1];
+  const double* ring = a.sums + static_cast<size_t>(used % 3) * kd;
+  const int32_t* cring = a.cnt + static_cast<size_t>(used % 3) * k;
+  int* cnt_l = reinterpret_cast<int*>(L.B + pl.cntl);
+  if (a.sums_in_lds) {
+    double* stage = reinterpret_cast<double*>(L.B + pl.sums);
+    const int d = a.d;
+    const int ld = sums_ld(d);
+#pragma unroll 4
+    for (int e = tid; e < kd; e += kBlock) {
+      const int j = e / d;
+      stage[j * ld + (e - j * d)] = ring[e];
+    }
+  }
+  for (int j = tid; j < k; j += kBlock) cnt_l[j] = cring[j];
+  return block_sum_f64<kBlock>(v, L.tmpd);
+}
+
+// New centroids from the gathered sums: the mean of each non-empty cluster as
+// an FP64 sum / count (kept as FP64 means, rounded to FP32 for the distance
 // kernels); an empty cluster turns degenerate.  Returns the largest Euclidean
 // move of a surviving centroid, measured between FP64 means.  Every workgroup
-// computes the same values and writes the same bits into c64[it % 2]; the
-// previous means are read from the other half.
+// computes the same values.  The FP64 means live in LDS when they fit,
+// otherwise in c64[it % 2] (every workgroup writes the same bits; the
+// previous means are read from the other half).
 template <int DM>
-__device__ double update_centroids(const SolverArgs& a, Lds& L, uint32_t used, int it) {
+__device__ __forceinline__ double update_centroids(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint32_t used,
+                                   int it) {
   const int tid = threadIdx.x;
   const int d = a.d;
   const int k = a.k;
   const double* ring = a.sums + static_cast<size_t>(used % 3) * k * d;
-  const int32_t* cring = a.cnt + static_cast<size_t>(used % 3) * k;
-  const double* c_old = a.c64 + static_cast<size_t>((it + 1) & 1) * k * d;
-  double* c_new = a.c64 + static_cast<size_t>(it & 1) * k * d;
+  const double* c_old = a.c64_in_lds ? L.c64 : a.c64 + static_cast<size_t>((it + 1) & 1) * k * d;
+  double* c_new = a.c64_in_lds ? L.c64 : a.c64 + static_cast<size_t>(it & 1) * k * d;
+  const int* cnt_l = reinterpret_cast<const int*>(L.B + pl.cntl);
+  // staged sums, overwritten in place by the squared coordinate moves
+  double* dsq = a.sums_in_lds ? reinterpret_cast<double*>(L.B + pl.sums) : nullptr;
+  const int ld = sums_ld(d);
+  if (tid == 0) L.misc[3] = 0;
+  if (dsq) {
+    for (int e = tid; e < k * d; e += kBlock) {
+      const int j = e / d;
+      const int c = cnt_l[j];
+      if (L.degf[j] || c == 0) continue;
+      const int q = j * ld + (e - j * d);
+      const double mean = dsq[q] / static_cast<double>(c);
+      const double diff = mean - c_old[e];
+      dsq[q] = __dmul_rn(diff, diff);
+      c_new[e] = mean;
+      L.C[j * DM + (e - j * d)] = static_cast<float>(mean);
+    }
+  }
+  __syncthreads();
   double local = 0.0;
   for (int j = tid; j < k; j += kBlock) {
     if (L.degf[j]) continue;
-    const int c = cring[j];
+    const int c = cnt_l[j];
     float* cj = L.C + j * DM;
     if (c == 0) {
       L.degf[j] = 1;
+      L.misc[3] = 1;
       for (int tdim = 0; tdim < d; ++tdim) cj[tdim] = __builtin_nanf("");
       continue;
     }
     double moved = 0.0;
-    for (int tdim = 0; tdim < d; ++tdim) {
-      const double mean = ring[j * d + tdim] / static_cast<double>(c);
-      const double diff = mean - c_old[j * d + tdim];
-      moved = __dadd_rn(moved, __dmul_rn(diff, diff));
-      c_new[j * d + tdim] = mean;
-      cj[tdim] = static_cast<float>(mean);
+    if (dsq) {
+      for (int tdim = 0; tdim < d; ++tdim) moved = __dadd_rn(moved, dsq[j * ld + tdim]);
+    } else {
+      for (int tdim = 0; tdim < d; ++tdim) {
+        const double mean = ring[j * d + tdim] / static_cast<double>(c);
+        const double diff = mean - c_old[j * d + tdim];
+        moved = __dadd_rn(moved, __dmul_rn(diff, diff));
+        c_new[j * d + tdim] = mean;
+        cj[tdim] = static_cast<float>(mean);
+      }
     }
     moved = sqrt(moved);
     local = moved > local ? moved : local;
@@ -679,42 +900,47 @@ __device__ double update_centroids(const SolverArgs& a, Lds& L, uint32_t used, i
     for (int w = 0; w < kWavesPerBlock; ++w) mx = L.tmpd[w] > mx ? L.tmpd[w] : mx;
     L.miscd[1] = mx;
   }
-  rebuild_active(L, k);
+  __syncthreads();
+  if (L.misc[3]) rebuild_active(L, k);  // a cluster emptied this round
   const double shift = L.miscd[1];
   __syncthreads();
   return shift;
 }
 
 template <int DM>
-__device__ bool lloyd_phase(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint32_t& pass,
-                            int64_t r0, int64_t r1, double& f_out, int& passes_out, int64_t& nd) {
+__device__ __forceinline__ bool lloyd_phase(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint32_t& pass,
+                            int64_t r0, int64_t r1, bool cached, const RowCache<DM>& rc,
+                            double& f_out, int& passes_out, int64_t& nd) {
   double f_prev = __builtin_inf();
   double f = 0.0;
   int passes = 0;
   bool by_objective = false;
-  // FP64 means start as the FP32 start centroids (identical writes from every
-  // workgroup; first read after the next grid barrier)
-  for (int e = threadIdx.x; e < a.k * a.d; e += kBlock) {
-    const int j = e / a.d;
-    a.c64[e] = static_cast<double>(L.C[j * DM + (e - j * a.d)]);
+  const int d = a.d;
+  // FP64 means start as the FP32 start centroids
+  double* c0 = a.c64_in_lds ? L.c64 : a.c64;
+  for (int e = threadIdx.x; e < a.k * d; e += kBlock) {
+    const int j = e / d;
+    c0[e] = static_cast<double>(L.C[j * DM + (e - j * d)]);
   }
   for (int it = 1; it <= a.max_iter; ++it) {
     const int na = L.misc[0];
-    if (!assign_pass<DM>(a, pl, L, pass, r0, r1, true, f)) return false;
+    if (!assign_pass<DM>(a, pl, L, pass, r0, r1, true, cached, rc)) return false;
     const uint32_t used = pass++;
     ++passes;
     nd += a.s * na;
+    f = gather_pass(a, pl, L, used);
     if (a.stop_rule == BM_STOP_REL_OBJ && it > 1 && (f_prev - f) <= a.tol * f_prev) {
       by_objective = true;
       break;
     }
-    const double shift = update_centroids<DM>(a, L, used, it);
+    const double shift = update_centroids<DM>(a, pl, L, used, it);
     f_prev = f;
     if (a.stop_rule == BM_STOP_SHIFT && shift < a.tol) break;
   }
   if (!by_objective) {
     const int na = L.misc[0];
-    if (!assign_pass<DM>(a, pl, L, pass, r0, r1, false, f)) return false;
+    if (!assign_pass<DM>(a, pl, L, pass, r0, r1, false, cached, rc)) return false;
+    f = gather_pass(a, pl, L, pass);
     ++pass;
     ++passes;
     nd += a.s * na;
@@ -727,7 +953,7 @@ __device__ bool lloyd_phase(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint
 // ---------------------------------------------------------------------------
 
 template <int DM>
-__device__ void load_incumbent(const SolverArgs& a, Lds& L) {
+__device__ __forceinline__ void load_incumbent(const SolverArgs& a, Lds& L) {
   const int d = a.d;
   const int k = a.k;
   for (int e = threadIdx.x; e < k * DM; e += kBlock) {
@@ -740,7 +966,7 @@ __device__ void load_incumbent(const SolverArgs& a, Lds& L) {
 }
 
 template <int DM>
-__device__ void store_incumbent(const SolverArgs& a, Lds& L, double f) {
+__device__ __forceinline__ void store_incumbent(const SolverArgs& a, Lds& L, double f) {
   const int d = a.d;
   const int k = a.k;
   for (int e = threadIdx.x; e < k * d; e += kBlock) {
@@ -757,7 +983,7 @@ __device__ void store_incumbent(const SolverArgs& a, Lds& L, double f) {
 template <int DM>
 __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.cand_cap, a.sums_in_lds != 0);
+  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds != 0, a.c64_in_lds != 0);
   Lds L = carve(lds_raw, pl);
   const int tid = threadIdx.x;
   const int g = blockIdx.x;
@@ -767,7 +993,6 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
   const int64_t r1 = imin64(a.s, r0 + rpw);
 
   int64_t c_passes = 0, c_reseeded = 0, c_replaced = 0, c_nd = 0, c_samples = 0, c_hist = 0;
-  int64_t c_bound = 0;
   uint32_t pass = 0;
   bool ok = true;
 
@@ -785,13 +1010,24 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
       if (!ok) break;
     }
     load_incumbent<DM>(a, L);
+    // this workgroup's sample rows stay in registers for the whole sample
+    // when the chunk is a single tile
+    // (only when a sample exists and a phase that reads it will run)
+    RowCache<DM> rc;
+    const bool uses_rows = a.P != nullptr && (a.do_seed || a.do_lloyd || a.do_keep);
+    const bool cached = uses_rows && RowCache<DM>::kRows > 0 && (r1 - r0) <= kBlock;
+    if (cached) {
+      const int64_t i = r0 + tid;
+      if (i < r1) load_row_f32<DM>(a.P + static_cast<size_t>(i) * a.d, a.d, rc.x[0]);
+    }
     double f_ref = 0.0;
     if (a.do_keep) {
       if (a.cmp_rule == BM_CMP_RESAMPLE) {
         if (L.misc[0] > 0) {
-          ok = assign_pass<DM>(a, pl, L, pass, r0, r1, false, f_ref);
-          ++pass;
+          ok = assign_pass<DM>(a, pl, L, pass, r0, r1, false, cached, rc);
           if (!ok) break;
+          f_ref = gather_pass(a, pl, L, pass);
+          ++pass;
         } else {
           f_ref = __builtin_inf();
         }
@@ -800,13 +1036,13 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
       }
     }
     if (a.do_seed && L.misc[0] < a.k) {
-      ok = reseed_phase<DM>(a, L, t, r0, r1, c_nd, c_reseeded, c_bound);
+      ok = reseed_phase<DM>(a, L, t, r0, r1, cached, rc, c_nd, c_reseeded);
       if (!ok) break;
     }
     double f = 0.0;
     int passes = 0;
     if (a.do_lloyd) {
-      ok = lloyd_phase<DM>(a, pl, L, pass, r0, r1, f, passes, c_nd);
+      ok = lloyd_phase<DM>(a, pl, L, pass, r0, r1, cached, rc, f, passes, c_nd);
       if (!ok) break;
       c_passes += passes;
     }
@@ -846,9 +1082,8 @@ int padded_dim(int d) {
   return -1;
 }
 
-size_t solver_lds_bytes(int dm, int k, int d, int grid, int cand_cap, bool sums_in_lds) {
-  (void)grid;
-  return plan_lds(dm, k, d, cand_cap, sums_in_lds).total;
+size_t solver_lds_bytes(int dm, int k, int d, bool sums_in_lds, bool c64_in_lds) {
+  return plan_lds(dm, k, d, sums_in_lds, c64_in_lds).total;
 }
 
 static const void* solver_fn(int dm) {
@@ -894,6 +1129,14 @@ bm_status solver_max_grid(int dm, size_t lds, int* max_grid) {
 }
 
 bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t stream) {
+  // every buffer a requested phase touches must exist
+  const bool rows = a.do_seed || a.do_lloyd || a.do_keep || a.do_gather;
+  if ((rows && !a.P) || (a.do_gather && !a.X) || (a.do_sample && (!a.idx || !a.cand_key ||
+      !a.cand_idx || !a.wg_lo || !a.wg_off || !a.thr || !a.hist || !a.cand_count)) ||
+      (rows && (!a.labels || !a.w)) || !a.Cinc || !a.deg_inc || !a.f_opt || !a.c64 || !a.sums ||
+      !a.cnt || !a.sse_part || !a.wsum || !a.phi_part || !a.cand || !a.counters || !a.bar ||
+      !a.err || !a.sample_f || grid < 1 || grid > kMaxGrid)
+    return set_error(BM_EINVAL, "solver launch with a missing buffer or bad grid %d", grid);
   const int dm = padded_dim(a.d);
   const void* fn = solver_fn(dm);
   if (!fn) return set_error(BM_ENOTSUP, "dimension %d exceeds the solver's limit of 256", a.d);
@@ -911,6 +1154,28 @@ bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t s
     return set_error(BM_EDEVICE, "cooperative launch failed (grid %d, LDS %zu B): %s", grid, lds,
                      hipGetErrorString(e));
   return BM_OK;
+}
+
+}  // namespace bm
+
+namespace bm {
+
+// Key window that holds the s-th smallest of n independent uniform 64-bit
+// keys with overwhelming probability: its rank is s on average with standard
+// deviation sqrt(s (1 - s/n)); the window spans 8 deviations plus 64 ranks on
+// either side, mapped to key values.  The candidate list holds the expected
+// window count with ample slack; a miss falls back to exact histogram passes.
+void sampler_window(int64_t n, int64_t s, uint64_t* lo, uint64_t* hi, int64_t* cap) {
+  const double nn = static_cast<double>(n), ss = static_cast<double>(s);
+  const double sigma = sqrt(ss * (1.0 - ss / nn));
+  const double delta = 8.0 * sigma + 64.0;
+  const double lo_rank = ss - delta, hi_rank = ss + delta;
+  *lo = lo_rank <= 0.0 ? 0ull : static_cast<uint64_t>(ldexp(lo_rank / nn, 64));
+  *hi = hi_rank >= nn ? ~0ull : static_cast<uint64_t>(ldexp(hi_rank / nn, 64));
+  const double expect = 2.0 * delta + 1.0;
+  double c = expect + 8.0 * sqrt(expect) + 4096.0;
+  if (c > nn) c = nn;
+  *cap = static_cast<int64_t>(c);
 }
 
 }  // namespace bm
