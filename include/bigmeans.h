@@ -103,6 +103,12 @@ typedef struct bm_stats {
   double f_opt;           /* objective of the incumbent on its own sample         */
   double ms_solver;       /* device time of the sample loop                       */
   double ms_final;        /* device time of the final assignment pass             */
+  double ms_sampling;     /* share of ms_solver spent drawing and gathering samples */
+  double ms_seeding;      /* ... in K-means++ reseeding                           */
+  double ms_lloyd;        /* ... in K-means on the samples                        */
+  double ms_lloyd_pass;   /* ... of which assignment passes (incl. their barrier) */
+  double ms_lloyd_post;   /* ... of which reading the reductions + updating        */
+  double ms_lloyd_wait;   /* ... of which waiting in the assignment-pass barrier  */
 } bm_stats;
 
 /* Fill *opt with defaults (struct_size set).  Returns BM_EINVAL on NULL. */

@@ -47,7 +47,10 @@ class Stats(ct.Structure):
                 ("replacements", ct.c_int32), ("grid", ct.c_int32),
                 ("lloyd_iters", ct.c_int64), ("reseeded", ct.c_int64), ("n_d", ct.c_int64),
                 ("boundary_draws", ct.c_int64), ("f_opt", ct.c_double),
-                ("ms_solver", ct.c_double), ("ms_final", ct.c_double)]
+                ("ms_solver", ct.c_double), ("ms_final", ct.c_double),
+                ("ms_sampling", ct.c_double), ("ms_seeding", ct.c_double),
+                ("ms_lloyd", ct.c_double), ("ms_lloyd_pass", ct.c_double),
+                ("ms_lloyd_post", ct.c_double), ("ms_lloyd_wait", ct.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}

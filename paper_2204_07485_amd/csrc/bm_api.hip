@@ -14,6 +14,7 @@ namespace bm {
 // errors
 
 static thread_local char g_err[512] = "";
+static thread_local int64_t g_last_counters[kNumCounters];
 
 bm_status set_error(bm_status code, const char* fmt, ...) {
   va_list ap;
@@ -194,7 +195,7 @@ struct SolverBuffers {
 };
 
 // Lay out every solver buffer; with base == nullptr only the size is computed.
-static void layout_solver(char* base, int64_t s, int d, int k, int T, int64_t cand_cap, bool own_P,
+static void layout_solver(char* base, int64_t n, int64_t s, int d, int k, int T, int64_t cand_cap, bool own_P,
                           bool own_idx, bool own_labels, bool own_inc, int final_grid,
                           SolverBuffers* b) {
   Layout L;
@@ -218,6 +219,7 @@ static void layout_solver(char* base, int64_t s, int d, int k, int T, int64_t ca
   a.wg_off = L.take<uint32_t>(kMaxGrid);
   a.cand_key = L.take<uint64_t>(cand_cap);
   a.cand_idx = L.take<int32_t>(cand_cap);
+  a.selcode = L.take<uint8_t>(n);
   a.w = L.take<double>(s);
   a.sample_f = L.take<double>(T > 0 ? T : 1);
   float* P = L.take<float>(own_P ? static_cast<size_t>(s) * d : 1);
@@ -238,16 +240,17 @@ static void layout_solver(char* base, int64_t s, int d, int k, int T, int64_t ca
   b->bytes = L.off + 256;
 }
 
-static bm_status prepare_solver(hipStream_t stream, int64_t s, int d, int k, int T, int64_t cand_cap,
+static bm_status prepare_solver(hipStream_t stream, int64_t n, int64_t s, int d, int k, int T,
+                                int64_t cand_cap,
                                 bool own_P, bool own_idx, bool own_labels, bool own_inc,
                                 int final_grid, SolverBuffers* b) {
   SolverArgs keep = b->a;
-  layout_solver(nullptr, s, d, k, T, cand_cap, own_P, own_idx, own_labels, own_inc, final_grid, b);
+  layout_solver(nullptr, n, s, d, k, T, cand_cap, own_P, own_idx, own_labels, own_inc, final_grid, b);
   bm_status st = BM_OK;
   char* base = static_cast<char*>(scratch_get(b->bytes, stream, &st));
   if (!base) return st;
   b->a = keep;
-  layout_solver(base, s, d, k, T, cand_cap, own_P, own_idx, own_labels, own_inc, final_grid, b);
+  layout_solver(base, n, s, d, k, T, cand_cap, own_P, own_idx, own_labels, own_inc, final_grid, b);
   BM_HIP(hipMemsetAsync(base, 0, b->ctrl_bytes, stream));
   if (final_grid > 0) BM_HIP(hipMemsetAsync(b->done, 0, sizeof(unsigned int), stream));
   return BM_OK;
@@ -302,6 +305,14 @@ const char* bm_last_error(void) { return g_err; }
 
 int32_t bm_abi_version(void) { return BM_ABI_VERSION; }
 
+// Raw per-phase counters of the last bigmeans_fit on this thread (diagnostics;
+// not declared in the public header).
+int32_t bm_debug_counters(int64_t* out, int32_t n) {
+  if (!out || n < 1) return BM_EINVAL;
+  for (int i = 0; i < n && i < kNumCounters; ++i) out[i] = g_last_counters[i];
+  return BM_OK;
+}
+
 bm_status bm_release_scratch(void) {
   std::lock_guard<std::mutex> lock(g_mu);
   (void)hipDeviceSynchronize();
@@ -335,7 +346,7 @@ bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s
   const int final_grid = final_pass ? assign_grid(n) : 0;
   SolverBuffers b;
   memset(&b.a, 0, sizeof b.a);
-  if ((st = prepare_solver(stream, s, d, k, n_samples, sp.cand_cap, true, true, true, true,
+  if ((st = prepare_solver(stream, n, s, d, k, n_samples, sp.cand_cap, true, true, true, true,
                            final_grid, &b)) != BM_OK)
     return st;
   SolverArgs& a = b.a;
@@ -405,6 +416,7 @@ bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s
     BM_HIP(hipMemcpyAsync(o.sample_f, a.sample_f, sizeof(double) * n_samples, hipMemcpyDeviceToHost, stream));
   int32_t code = 0;
   st = check_solver_error(a, stream, &code);
+  memcpy(g_last_counters, counters, sizeof counters);
   const float ms_solver = elapsed_ms(ev[0], ev[1]);
   const float ms_final = elapsed_ms(ev[1], ev[2]);
   for (auto& e : ev) (void)hipEventDestroy(e);
@@ -422,6 +434,16 @@ bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s
     stats->f_opt = fopt;
     stats->ms_solver = ms_solver;
     stats->ms_final = ms_final;
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0) {
+      stats->ms_sampling = static_cast<double>(counters[kCntTicksSample]) / khz;
+      stats->ms_seeding = static_cast<double>(counters[kCntTicksSeed]) / khz;
+      stats->ms_lloyd = static_cast<double>(counters[kCntTicksLloyd]) / khz;
+      stats->ms_lloyd_pass = static_cast<double>(counters[kCntTicksPass]) / khz;
+      stats->ms_lloyd_post = static_cast<double>(counters[kCntTicksPost]) / khz;
+      stats->ms_lloyd_wait = static_cast<double>(counters[kCntTicksBarrier]) / khz;
+    }
   }
   return BM_OK;
 }
@@ -489,7 +511,7 @@ static bm_status run_solver_on_sample(const float* P, int64_t s, int32_t d, int3
   b.a.P = const_cast<float*>(P);
   b.a.Cinc = C;
   b.a.labels = labels;
-  if ((st = prepare_solver(stream, s, d, k, 1, sp.cand_cap, false, true, labels == nullptr, false,
+  if ((st = prepare_solver(stream, s, s, d, k, 1, sp.cand_cap, false, true, labels == nullptr, false,
                            0, &b)) != BM_OK)
     return st;
   SolverArgs& a = b.a;
@@ -573,7 +595,7 @@ bm_status bm_sample_indices(int64_t n, int64_t s, uint64_t seed, int32_t t, int3
   SolverBuffers b;
   memset(&b.a, 0, sizeof b.a);
   b.a.idx = idx;
-  if ((st = prepare_solver(stream, s, 1, 1, 1, sp.cand_cap, false, false, true, true, 0, &b)) != BM_OK)
+  if ((st = prepare_solver(stream, n, s, 1, 1, 1, sp.cand_cap, false, false, true, true, 0, &b)) != BM_OK)
     return st;
   SolverArgs& a = b.a;
   a.n = n;

@@ -12,7 +12,7 @@ namespace bm {
 
 constexpr int kMaxTrials = 8;       // K-means++ candidates per centre
 constexpr int kMaxGrid = 1024;      // solver workgroups
-constexpr int kNumCounters = 16;
+constexpr int kNumCounters = 24;
 constexpr unsigned int kDefaultSpinLimit = 1u << 24;
 
 enum Counter {
@@ -22,7 +22,17 @@ enum Counter {
   kCntND = 3,          // distance evaluations at sample level
   kCntBoundary = 4,    // D^2 draws within rounding of a running-sum boundary
   kCntSamples = 5,     // samples processed
-  kCntSelectPasses = 6 // histogram passes of the sampler (all samples)
+  kCntSelectPasses = 6, // histogram passes of the sampler (all samples)
+  kCntTicksSample = 8,   // device wall-clock ticks spent per phase (workgroup 0)
+  kCntTicksSeed = 9,
+  kCntTicksLloyd = 10,
+  kCntTicksPass = 11,    // Lloyd: assign + accumulate + flush + barrier
+  kCntTicksPost = 12,    // Lloyd: gather of the reductions + centroid update
+  kCntTicksBarrier = 13, // Lloyd: waiting in the pass barrier
+  kCntTicksCollect = 14, // sampler: collect pass / its barrier wait / select / emit
+  kCntTicksCollectWait = 15,
+  kCntTicksSelect = 16,
+  kCntTicksEmit = 17,
 };
 
 enum SolverError {
@@ -84,6 +94,7 @@ struct SolverArgs {
   uint64_t* cand_key;        // cand_cap
   int32_t* cand_idx;         // cand_cap
   uint32_t* cand_count;      // 1
+  uint8_t* selcode;          // n: point below (1), inside (2), above (0) the key window
   uint64_t* thr;             // 2: threshold key, index
   // outputs / control
   int32_t* sample_idx_out;   // T x s or null

@@ -28,6 +28,7 @@ namespace bm {
 namespace {
 
 constexpr int kHistBins = 256;
+constexpr int kCandStage = 4096;  // sampler candidates staged in LDS per workgroup
 
 struct Lds {
   float* C;          // k x DM, padded with zeros past d
@@ -52,7 +53,7 @@ __host__ __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) &
 
 struct LdsPlan {
   size_t C, act, degf, tmpi, tmpd, misc, misc64, miscd, c64, B;
-  size_t hist, selc, total_sampling;
+  size_t hist, selc, ckey, cidx, total_sampling;
   size_t sums, cntl, total_lloyd;
   size_t total;
 };
@@ -74,6 +75,8 @@ __host__ __device__ inline LdsPlan plan_lds(int dm, int k, int d, bool sums_in_l
   size_t b = 0;
   p.hist = b; b = align16(b + sizeof(unsigned int) * kHistBins);
   p.selc = b; b = align16(b + sizeof(unsigned int) * kMaxGrid);
+  p.ckey = b; b = align16(b + sizeof(uint64_t) * kCandStage);
+  p.cidx = b; b = align16(b + sizeof(int32_t) * kCandStage);
   // K-means++: scan staging (kBlock doubles) and the candidate rows
   const size_t seed_stage = sizeof(double) * kBlock + sizeof(float) * kMaxTrials * size_t(dm);
   if (b < seed_stage) b = seed_stage;
@@ -150,26 +153,55 @@ __device__ __forceinline__ bool pair_le(uint64_t k, int64_t i, uint64_t tk, int6
   return k < tk || (k == tk && i <= ti);
 }
 
-// Append (key, index) to the candidate list with one atomic per wavefront.
-__device__ __forceinline__ void append_candidate(const SolverArgs& a, bool pred, uint64_t key,
-                                                 int64_t i) {
+// Append (key, index) to this workgroup's candidate buffer in LDS (one LDS
+// atomic per wavefront); entries beyond the buffer go straight to the global
+// list.  flush_candidates moves the buffer to the global list with a single
+// global atomic per workgroup.
+__device__ __forceinline__ void append_candidate(const SolverArgs& a, const LdsPlan& pl, Lds& L,
+                                                 bool pred, uint64_t key, int64_t i) {
   const unsigned long long mask = __ballot(pred);
   if (mask == 0ull) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int leader = __builtin_ctzll(mask);
   unsigned int base = 0;
-  if (lane == leader) base = atomicAdd(a.cand_count, static_cast<unsigned int>(__popcll(mask)));
+  if (lane == leader) base = atomicAdd(reinterpret_cast<unsigned int*>(&L.misc[4]),
+                                       static_cast<unsigned int>(__popcll(mask)));
   base = __shfl(base, leader, kWave);
   if (pred) {
-    const unsigned int rank = __popcll(mask & ((1ull << lane) - 1ull));
-    const unsigned int slot = base + rank;
-    if (slot < static_cast<unsigned int>(a.cand_cap)) {
-      a.cand_key[slot] = key;
-      a.cand_idx[slot] = static_cast<int32_t>(i);
+    const unsigned int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+    if (slot < static_cast<unsigned int>(kCandStage)) {
+      reinterpret_cast<uint64_t*>(L.B + pl.ckey)[slot] = key;
+      reinterpret_cast<int32_t*>(L.B + pl.cidx)[slot] = static_cast<int32_t>(i);
+    } else {
+      const unsigned int gs = atomicAdd(a.cand_count, 1u);
+      if (gs < static_cast<unsigned int>(a.cand_cap)) {
+        a.cand_key[gs] = key;
+        a.cand_idx[gs] = static_cast<int32_t>(i);
+      }
     }
   }
 }
 
+__device__ __forceinline__ void flush_candidates(const SolverArgs& a, const LdsPlan& pl, Lds& L) {
+  __syncthreads();
+  const unsigned int cnt = static_cast<unsigned int>(L.misc[4]);
+  const unsigned int nl = cnt < static_cast<unsigned int>(kCandStage) ? cnt : kCandStage;
+  if (threadIdx.x == 0) L.misc[5] = nl ? static_cast<int>(atomicAdd(a.cand_count, nl)) : 0;
+  __syncthreads();
+  const unsigned int gb = static_cast<unsigned int>(L.misc[5]);
+  const uint64_t* ck = reinterpret_cast<const uint64_t*>(L.B + pl.ckey);
+  const int32_t* ci = reinterpret_cast<const int32_t*>(L.B + pl.cidx);
+  for (unsigned int r = threadIdx.x; r < nl; r += kBlock) {
+    if (gb + r < static_cast<unsigned int>(a.cand_cap)) {
+      a.cand_key[gb + r] = ck[r];
+      a.cand_idx[gb + r] = ci[r];
+    }
+  }
+}
+
+// Write sampled point i at position pos: index, and its row gathered into P
+// (the whole row is loaded into registers first, so its loads overlap).
+template <int DM>
 __device__ __forceinline__ void emit_point(const SolverArgs& a, int tt, int64_t pos, int64_t i) {
   if (pos < 0 || pos >= a.s) {  // inconsistent bookkeeping: never write out of bounds
     atomicCAS(a.err, 0, kErrSelect);
@@ -179,13 +211,21 @@ __device__ __forceinline__ void emit_point(const SolverArgs& a, int tt, int64_t 
   if (a.sample_idx_out) a.sample_idx_out[static_cast<size_t>(tt) * a.s + pos] = static_cast<int32_t>(i);
   if (a.do_gather) {
     const int d = a.d;
+    float x[DM];
+    if (a.x_bf16)
+      load_row_bf16<DM>(static_cast<const uint16_t*>(a.X) + static_cast<size_t>(i) * d, d, x);
+    else
+      load_row_f32<DM>(static_cast<const float*>(a.X) + static_cast<size_t>(i) * d, d, x);
     float* dst = a.P + static_cast<size_t>(pos) * d;
-    if (a.x_bf16) {
-      const uint16_t* src = static_cast<const uint16_t*>(a.X) + static_cast<size_t>(i) * d;
-      for (int t = 0; t < d; ++t) dst[t] = bf16_bits_to_float(src[t]);
+    if ((d & 3) == 0) {
+#pragma unroll
+      for (int q = 0; q < DM / 4; ++q)
+        if (4 * q < d)
+          reinterpret_cast<float4*>(dst)[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
     } else {
-      const float* src = static_cast<const float*>(a.X) + static_cast<size_t>(i) * d;
-      for (int t = 0; t < d; ++t) dst[t] = src[t];
+#pragma unroll
+      for (int t = 0; t < DM; ++t)
+        if (t < d) dst[t] = x[t];
     }
   }
 }
@@ -206,6 +246,20 @@ __device__ __forceinline__ bool select_threshold(const SolverArgs& a, const LdsP
     if (tid == 0) set_err(a, kErrSelect);
     return false;
   }
+  // candidates read from LDS when they fit the stage, else from global memory
+  const bool staged = m <= kCandStage;
+  const uint64_t* ckey = staged ? reinterpret_cast<const uint64_t*>(L.B + pl.ckey) : a.cand_key;
+  const int32_t* cidx = staged ? reinterpret_cast<const int32_t*>(L.B + pl.cidx) : a.cand_idx;
+  if (staged) {
+    uint64_t* sk = reinterpret_cast<uint64_t*>(L.B + pl.ckey);
+    int32_t* si = reinterpret_cast<int32_t*>(L.B + pl.cidx);
+#pragma unroll 4
+    for (int64_t r = tid; r < m; r += kBlock) {
+      sk[r] = a.cand_key[r];
+      si[r] = a.cand_idx[r];
+    }
+    __syncthreads();
+  }
   uint64_t pre = 0;
   int nbits = 0;
   int64_t rem = need;  // rank inside the current prefix class
@@ -215,7 +269,7 @@ __device__ __forceinline__ bool select_threshold(const SolverArgs& a, const LdsP
     __syncthreads();
     const int shift = 56 - nbits;
     for (int64_t r = tid; r < m; r += kBlock) {
-      const uint64_t key = a.cand_key[r];
+      const uint64_t key = ckey[r];
       if (key_in_window(key, pre, nbits)) atomicAdd(&hist[(key >> shift) & 255u], 1u);
     }
     __syncthreads();
@@ -244,13 +298,13 @@ __device__ __forceinline__ bool select_threshold(const SolverArgs& a, const LdsP
   if (tid == 0) L.misc64[2] = -1;
   __syncthreads();
   for (int64_t r = tid; r < m; r += kBlock) {
-    const uint64_t key = a.cand_key[r];
+    const uint64_t key = ckey[r];
     if (!key_in_window(key, pre, nbits)) continue;
-    const int32_t idx = a.cand_idx[r];
+    const int32_t idx = cidx[r];
     int64_t rank = 0;
     if (cnt > 1) {
       for (int64_t r2 = 0; r2 < m; ++r2)
-        if (key_in_window(a.cand_key[r2], pre, nbits) && a.cand_idx[r2] < idx) ++rank;
+        if (key_in_window(ckey[r2], pre, nbits) && cidx[r2] < idx) ++rank;
     }
     if (rank == rem - 1) {
       L.misc64[2] = idx;
@@ -266,8 +320,8 @@ __device__ __forceinline__ bool select_threshold(const SolverArgs& a, const LdsP
   const uint64_t tk = static_cast<uint64_t>(L.misc64[3]);
   const int64_t ti = L.misc64[2];
   for (int64_t r = tid; r < m; r += kBlock) {
-    const uint64_t key = a.cand_key[r];
-    const int64_t idx = a.cand_idx[r];
+    const uint64_t key = ckey[r];
+    const int64_t idx = cidx[r];
     if (pair_le(key, idx, tk, ti)) atomicAdd(&selc[static_cast<int>((idx >> 1) / ppw)], 1u);
   }
   __syncthreads();
@@ -293,25 +347,38 @@ __device__ __forceinline__ bool select_threshold(const SolverArgs& a, const LdsP
 }
 
 // Collect pass over this workgroup's point pairs: count the keys below
-// [lo, hi] (inclusive) into wg_lo[g] and append the keys inside to the
-// candidate list.
-__device__ __forceinline__ void collect_pass(const SolverArgs& a, Lds& L, uint32_t t, int64_t p0, int64_t p1,
-                             uint64_t lo, uint64_t hi) {
+// [lo, hi] (inclusive) into wg_lo[g], append the keys inside to the candidate
+// list, and record per point whether its key is below (1), inside (2) or
+// above (0) the window.  Each thread takes a contiguous run of pairs.
+__device__ __forceinline__ void collect_pass(const SolverArgs& a, const LdsPlan& pl, Lds& L,
+                                             uint32_t t, int64_t p0, int64_t p1, uint64_t lo,
+                                             uint64_t hi) {
   const int tid = threadIdx.x;
   const int64_t n = a.n;
+  const int64_t per = (p1 - p0 + kBlock - 1) / kBlock;
+  const int64_t q0 = p0 + tid * per;
+  const int64_t q1 = imin64(p1, q0 + per);
+  if (tid == 0) L.misc[4] = 0;
+  __syncthreads();
   int lo_count = 0;
-  const int64_t tiles = (p1 - p0 + kBlock - 1) / kBlock;
-  for (int64_t tile = 0; tile < tiles; ++tile) {
-    const int64_t p = p0 + tile * kBlock + tid;
-    const bool v0 = p < p1;
+  for (int64_t step = 0; step < per; ++step) {  // uniform trip count for the ballots
+    const int64_t p = q0 + step;
+    const bool v0 = p < q1;
     const bool v1 = v0 && (2 * p + 1 < n);
     uint64_t k0 = 0, k1 = 0;
     if (v0) sample_key_pair(a.seed, t, static_cast<uint64_t>(p), k0, k1);
-    lo_count += (v0 && k0 < lo) ? 1 : 0;
-    lo_count += (v1 && k1 < lo) ? 1 : 0;
-    append_candidate(a, v0 && k0 >= lo && k0 <= hi, k0, 2 * p);
-    append_candidate(a, v1 && k1 >= lo && k1 <= hi, k1, 2 * p + 1);
+    const int c0 = !v0 ? 0 : (k0 < lo ? 1 : (k0 <= hi ? 2 : 0));
+    const int c1 = !v1 ? 0 : (k1 < lo ? 1 : (k1 <= hi ? 2 : 0));
+    lo_count += (c0 == 1) + (c1 == 1);
+    if (v1) {
+      reinterpret_cast<uint16_t*>(a.selcode)[p] = static_cast<uint16_t>(c0 | (c1 << 8));
+    } else if (v0) {
+      a.selcode[2 * p] = static_cast<uint8_t>(c0);
+    }
+    append_candidate(a, pl, L, c0 == 2, k0, 2 * p);
+    append_candidate(a, pl, L, c1 == 2, k1, 2 * p + 1);
   }
+  flush_candidates(a, pl, L);
   const int wg_lo = block_sum_i32<kBlock>(lo_count, L.tmpi);
   if (tid == 0) a.wg_lo[blockIdx.x] = static_cast<uint32_t>(wg_lo);
 }
@@ -322,6 +389,7 @@ __device__ __forceinline__ void collect_pass(const SolverArgs& a, Lds& L, uint32
 // 8 standard deviations of s/n of the key range, plus a margin) almost always
 // holds the threshold, so one collect pass suffices; otherwise MSB histogram
 // passes narrow an exact window first.
+template <int DM>
 __device__ __forceinline__ bool sample_phase(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint32_t t, int tt,
                              int64_t& hist_passes) {
   const int tid = threadIdx.x;
@@ -335,8 +403,15 @@ __device__ __forceinline__ bool sample_phase(const SolverArgs& a, const LdsPlan&
   unsigned int* hist = reinterpret_cast<unsigned int*>(L.B + pl.hist);
 
   // fast path: predicted window
-  collect_pass(a, L, t, p0, p1, a.win_lo, a.win_hi);
+  const uint64_t s0 = wall_clock64();
+  collect_pass(a, pl, L, t, p0, p1, a.win_lo, a.win_hi);
+  const uint64_t s1 = wall_clock64();
   if (!sync_grid(a)) return false;
+  const uint64_t s2 = wall_clock64();
+  if (g == 0 && tid == 0) {
+    a.counters[kCntTicksCollect] += static_cast<int64_t>(s1 - s0);
+    a.counters[kCntTicksCollectWait] += static_cast<int64_t>(s2 - s1);
+  }
   {
     const int g0 = 2 * tid;
     int v = 0;
@@ -349,7 +424,9 @@ __device__ __forceinline__ bool sample_phase(const SolverArgs& a, const LdsPlan&
       if (hit && !select_threshold(a, pl, L, below, m, ppw)) return false;
       if (tid == 0) __hip_atomic_store(a.cand_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    const uint64_t s3 = wall_clock64();
     if (!sync_grid(a)) return false;
+    if (g == 0 && tid == 0) a.counters[kCntTicksSelect] += static_cast<int64_t>(s3 - s2);
     if (!hit) {
       // exact fallback: histogram passes over the key prefixes
       uint64_t pre = 0;
@@ -405,7 +482,7 @@ __device__ __forceinline__ bool sample_phase(const SolverArgs& a, const LdsPlan&
       }
       const uint64_t lo = nbits ? pre << (64 - nbits) : 0ull;
       const uint64_t hi = nbits ? lo | (~0ull >> nbits) : ~0ull;
-      collect_pass(a, L, t, p0, p1, lo, hi);
+      collect_pass(a, pl, L, t, p0, p1, lo, hi);
       if (!sync_grid(a)) return false;
       if (g == 0) {
         const int64_t got = __hip_atomic_load(a.cand_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -420,26 +497,70 @@ __device__ __forceinline__ bool sample_phase(const SolverArgs& a, const LdsPlan&
     }
   }
 
-  // emit in index order and gather
+  // emit in index order and gather: each thread takes a contiguous run of
+  // pairs, counts its selected points from the codes (a key inside the window
+  // is recomputed and compared with the threshold pair), and writes them at
+  // its offset from one block-wide scan
   const uint64_t tk = a.thr[0];
   const int64_t ti = static_cast<int64_t>(a.thr[1]);
-  int64_t base = a.wg_off[g];
-  const int64_t tiles = (p1 - p0 + kBlock - 1) / kBlock;
-  for (int64_t tile = 0; tile < tiles; ++tile) {
-    const int64_t p = p0 + tile * kBlock + tid;
-    const bool v0 = p < p1;
-    const bool v1 = v0 && (2 * p + 1 < n);
-    uint64_t k0 = 0, k1 = 0;
-    if (v0) sample_key_pair(a.seed, t, static_cast<uint64_t>(p), k0, k1);
-    const int s0 = (v0 && pair_le(k0, 2 * p, tk, ti)) ? 1 : 0;
-    const int s1 = (v1 && pair_le(k1, 2 * p + 1, tk, ti)) ? 1 : 0;
-    int total = 0;
-    const int excl = block_exclusive_scan<kBlock, int>(s0 + s1, L.tmpi, total);
-    const int64_t pos = base + excl;
-    if (s0) emit_point(a, tt, pos, 2 * p);
-    if (s1) emit_point(a, tt, pos + s0, 2 * p + 1);
-    base += total;
+  const int64_t per = (p1 - p0 + kBlock - 1) / kBlock;
+  const int64_t q0 = p0 + tid * per;
+  const int64_t q1 = imin64(p1, q0 + per);
+  auto selected = [&](int64_t i, int code) -> bool {
+    if (code != 2) return code == 1;
+    uint64_t ke, ko;
+    sample_key_pair(a.seed, t, static_cast<uint64_t>(i >> 1), ke, ko);
+    return pair_le((i & 1) ? ko : ke, i, tk, ti);
+  };
+  const uint64_t s4 = wall_clock64();
+  const uint16_t* code2 = reinterpret_cast<const uint16_t*>(a.selcode);
+  auto codes_of = [&](int64_t p) -> int {  // both codes of pair p (odd n: last pair has one)
+    return (2 * p + 1 < n) ? static_cast<int>(code2[p]) : static_cast<int>(a.selcode[2 * p]);
+  };
+  // selection bits of this thread's points (up to 128), decided once
+  uint64_t bits_lo = 0, bits_hi = 0;
+  const bool fits = per <= 64;
+  int mine = 0;
+  if (fits) {
+#pragma unroll 4
+    for (int64_t p = q0; p < q1; ++p) {
+      const int c = codes_of(p);
+      const int j = static_cast<int>(2 * (p - q0));
+      const uint64_t b = (selected(2 * p, c & 255) ? 1ull : 0ull) |
+                         ((2 * p + 1 < n && selected(2 * p + 1, c >> 8)) ? 2ull : 0ull);
+      if (j < 64) bits_lo |= b << j;
+      else bits_hi |= b << (j - 64);
+    }
+    mine = __popcll(bits_lo) + __popcll(bits_hi);
+  } else {
+    for (int64_t p = q0; p < q1; ++p) {
+      const int c = codes_of(p);
+      mine += selected(2 * p, c & 255) ? 1 : 0;
+      if (2 * p + 1 < n) mine += selected(2 * p + 1, c >> 8) ? 1 : 0;
+    }
   }
+  int total = 0;
+  const int excl = block_exclusive_scan<kBlock, int>(mine, L.tmpi, total);
+  int64_t pos = static_cast<int64_t>(a.wg_off[g]) + excl;
+  if (fits) {
+    while (bits_lo) {
+      const int j = __builtin_ctzll(bits_lo);
+      bits_lo &= bits_lo - 1;
+      emit_point<DM>(a, tt, pos++, 2 * q0 + j);
+    }
+    while (bits_hi) {
+      const int j = __builtin_ctzll(bits_hi);
+      bits_hi &= bits_hi - 1;
+      emit_point<DM>(a, tt, pos++, 2 * q0 + 64 + j);
+    }
+  } else {
+    for (int64_t p = q0; p < q1; ++p) {
+      const int c = codes_of(p);
+      if (selected(2 * p, c & 255)) emit_point<DM>(a, tt, pos++, 2 * p);
+      if (2 * p + 1 < n && selected(2 * p + 1, c >> 8)) emit_point<DM>(a, tt, pos++, 2 * p + 1);
+    }
+  }
+  if (g == 0 && tid == 0) a.counters[kCntTicksEmit] += static_cast<int64_t>(wall_clock64() - s4);
   return sync_grid(a);
 }
 
@@ -791,7 +912,10 @@ __device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& 
       if (cnt_l[j]) atomicAdd(&cring[j], cnt_l[j]);
   }
   if (tid == 0) a.sse_part[(pass & 1u) * kMaxGrid + g] = wsse;
-  return sync_grid(a);
+  const uint64_t b0 = wall_clock64();
+  const bool ok = sync_grid(a);
+  if (g == 0 && tid == 0) a.counters[kCntTicksBarrier] += static_cast<int64_t>(wall_clock64() - b0);
+  return ok;
 }
 
 // After the barrier of pass `used`: read the objective partials, the cluster
@@ -910,7 +1034,8 @@ __device__ __forceinline__ double update_centroids(const SolverArgs& a, const Ld
 template <int DM>
 __device__ __forceinline__ bool lloyd_phase(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint32_t& pass,
                             int64_t r0, int64_t r1, bool cached, const RowCache<DM>& rc,
-                            double& f_out, int& passes_out, int64_t& nd) {
+                            double& f_out, int& passes_out, int64_t& nd, uint64_t& tk_pass,
+                            uint64_t& tk_post) {
   double f_prev = __builtin_inf();
   double f = 0.0;
   int passes = 0;
@@ -924,7 +1049,9 @@ __device__ __forceinline__ bool lloyd_phase(const SolverArgs& a, const LdsPlan& 
   }
   for (int it = 1; it <= a.max_iter; ++it) {
     const int na = L.misc[0];
+    const uint64_t c0t = wall_clock64();
     if (!assign_pass<DM>(a, pl, L, pass, r0, r1, true, cached, rc)) return false;
+    const uint64_t c1t = wall_clock64();
     const uint32_t used = pass++;
     ++passes;
     nd += a.s * na;
@@ -934,6 +1061,9 @@ __device__ __forceinline__ bool lloyd_phase(const SolverArgs& a, const LdsPlan& 
       break;
     }
     const double shift = update_centroids<DM>(a, pl, L, used, it);
+    const uint64_t c2t = wall_clock64();
+    tk_pass += c1t - c0t;
+    tk_post += c2t - c1t;
     f_prev = f;
     if (a.stop_rule == BM_STOP_SHIFT && shift < a.tol) break;
   }
@@ -993,6 +1123,7 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
   const int64_t r1 = imin64(a.s, r0 + rpw);
 
   int64_t c_passes = 0, c_reseeded = 0, c_replaced = 0, c_nd = 0, c_samples = 0, c_hist = 0;
+  uint64_t c_tsample = 0, c_tseed = 0, c_tlloyd = 0, c_tpass = 0, c_tpost = 0;
   uint32_t pass = 0;
   bool ok = true;
 
@@ -1005,10 +1136,13 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
 
   for (int tt = 0; ok && tt < a.T; ++tt) {
     const uint32_t t = static_cast<uint32_t>(a.t0 + tt);
+    uint64_t clk0 = wall_clock64();
     if (a.do_sample) {
-      ok = sample_phase(a, pl, L, t, tt, c_hist);
+      ok = sample_phase<DM>(a, pl, L, t, tt, c_hist);
       if (!ok) break;
     }
+    uint64_t clk1 = wall_clock64();
+    c_tsample += clk1 - clk0;
     load_incumbent<DM>(a, L);
     // this workgroup's sample rows stay in registers for the whole sample
     // when the chunk is a single tile
@@ -1035,17 +1169,21 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
         f_ref = *a.f_opt;
       }
     }
+    clk0 = wall_clock64();
     if (a.do_seed && L.misc[0] < a.k) {
       ok = reseed_phase<DM>(a, L, t, r0, r1, cached, rc, c_nd, c_reseeded);
       if (!ok) break;
     }
+    clk1 = wall_clock64();
+    c_tseed += clk1 - clk0;
     double f = 0.0;
     int passes = 0;
     if (a.do_lloyd) {
-      ok = lloyd_phase<DM>(a, pl, L, pass, r0, r1, cached, rc, f, passes, c_nd);
+      ok = lloyd_phase<DM>(a, pl, L, pass, r0, r1, cached, rc, f, passes, c_nd, c_tpass, c_tpost);
       if (!ok) break;
       c_passes += passes;
     }
+    c_tlloyd += wall_clock64() - clk1;
     if (a.do_keep) {
       if (f_ref > f) {
         if (g == 0) store_incumbent<DM>(a, L, f);
@@ -1064,6 +1202,11 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
     a.counters[kCntND] = c_nd;
     a.counters[kCntSamples] = c_samples;
     a.counters[kCntSelectPasses] = c_hist;
+    a.counters[kCntTicksSample] = static_cast<int64_t>(c_tsample);
+    a.counters[kCntTicksSeed] = static_cast<int64_t>(c_tseed);
+    a.counters[kCntTicksLloyd] = static_cast<int64_t>(c_tlloyd);
+    a.counters[kCntTicksPass] = static_cast<int64_t>(c_tpass);
+    a.counters[kCntTicksPost] = static_cast<int64_t>(c_tpost);
   }
 }
 
@@ -1131,7 +1274,7 @@ bm_status solver_max_grid(int dm, size_t lds, int* max_grid) {
 bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t stream) {
   // every buffer a requested phase touches must exist
   const bool rows = a.do_seed || a.do_lloyd || a.do_keep || a.do_gather;
-  if ((rows && !a.P) || (a.do_gather && !a.X) || (a.do_sample && (!a.idx || !a.cand_key ||
+  if ((rows && !a.P) || (a.do_gather && !a.X) || (a.do_sample && (!a.idx || !a.cand_key || !a.selcode ||
       !a.cand_idx || !a.wg_lo || !a.wg_off || !a.thr || !a.hist || !a.cand_count)) ||
       (rows && (!a.labels || !a.w)) || !a.Cinc || !a.deg_inc || !a.f_opt || !a.c64 || !a.sums ||
       !a.cnt || !a.sse_part || !a.wsum || !a.phi_part || !a.cand || !a.counters || !a.bar ||
