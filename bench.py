@@ -22,6 +22,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "solver_medium_hbm_counters.md")
+
+
+def source_hash():
+    """Hash of the kernel sources and the C header, to tell whether stored
+    profiler byte counts still describe the kernels being timed."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2204_07485_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "bigmeans.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernels changed since it was taken."""
+    if not os.path.exists(COUNTERS):
+        return None, None
+    vals = {}
+    with open(COUNTERS) as fh:
+        for line in fh:
+            if ":" in line and line.split(":")[0] in ("source-hash", "traffic_mb_solver",
+                                                       "traffic_mb_final"):
+                key, val = line.split(":", 1)
+                vals[key.strip()] = val.strip()
+    if vals.get("source-hash") != source_hash():
+        return None, None
+    return float(vals["traffic_mb_solver"]) * 1e6, float(vals["traffic_mb_final"]) * 1e6
 
 
 def parse():
@@ -32,6 +65,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=12,
                     help="samples the CPU oracle runs for its bounded baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after timing, run a plain 1 GiB device copy three times (a known "
+                         "amount of HBM traffic for scaling profiler byte counters)")
     return ap.parse_args()
 
 
@@ -115,6 +151,7 @@ def main():
     final_flops = n * k * d * 2
     achieved = solver_bytes / (solver_ms * 1e-3) / 1e9
     final_gbs = final_bytes / (final_ms * 1e-3) / 1e9
+    traffic_solver, traffic_final = measured_traffic()
 
     line = {
         "metric": "Big-means time-to-oracle-SSE; assign TFLOP/s & HBM GB/s; p50/p99 job latency",
@@ -143,16 +180,24 @@ def main():
         "fit_ms_p99": float(np.percentile(wall, 99)),
         "roofline": {"bound": "hbm", "kernel": "solver_kernel<16> (sample loop)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_solver,
                      "ms_per_launch": solver_ms, "algorithmic_bytes": solver_bytes,
                      "tflops": solver_flops / (solver_ms * 1e-3) / 1e12},
         "roofline_final_pass": {"bound": "hbm", "kernel": "assign_kernel<16,f32>",
                                 "achieved": final_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                "frac": final_gbs / HBM_PEAK_GBS, "ms_per_launch": final_ms,
+                                "frac": final_gbs / HBM_PEAK_GBS, "traffic": traffic_final,
+                                "ms_per_launch": final_ms,
                                 "algorithmic_bytes": final_bytes,
                                 "tflops": final_flops / (final_ms * 1e-3) / 1e12},
         "stats": st,
     }
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         print("cpu baseline (oracle, 1 thread) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(X, W, args.cpu_samples)

@@ -206,8 +206,8 @@ static void layout_solver(char* base, int64_t n, int64_t s, int d, int k, int T,
   a.counters = L.take<int64_t>(kNumCounters);
   a.cand_count = L.take<uint32_t>(1);
   a.hist = L.take<uint32_t>(3 * 256);
-  a.sums = L.take<double>(3 * static_cast<size_t>(k) * d);
-  a.cnt = L.take<int32_t>(3 * static_cast<size_t>(k));
+  a.sums = L.take<double>(3 * static_cast<size_t>(kReplicas) * k * d);
+  a.cnt = L.take<int32_t>(3 * static_cast<size_t>(kReplicas) * k);
   b->ctrl_bytes = L.off;
   a.c64 = L.take<double>(2 * static_cast<size_t>(k) * d);
   a.thr = L.take<uint64_t>(2);

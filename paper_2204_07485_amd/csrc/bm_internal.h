@@ -11,6 +11,8 @@
 namespace bm {
 
 constexpr int kMaxTrials = 8;       // K-means++ candidates per centre
+constexpr int kReplicas = 1;        // copies of the cluster-sum accumulators (workgroup g
+                                    // adds into copy g % kReplicas); one measured best
 constexpr int kMaxGrid = 1024;      // solver workgroups
 constexpr int kNumCounters = 24;
 constexpr unsigned int kDefaultSpinLimit = 1u << 24;
@@ -81,8 +83,8 @@ struct SolverArgs {
   double* f_opt;             // 1
   // reductions
   double* c64;               // 2 x k x d: FP64 centroid means (old / new)
-  double* sums;              // 3 x k x d ring
-  int32_t* cnt;              // 3 x k ring
+  double* sums;              // 3 x kReplicas x k x d ring
+  int32_t* cnt;              // 3 x kReplicas x k ring
   double* sse_part;          // 2 x kMaxGrid
   double* wsum;              // kMaxGrid
   double* phi_part;          // kMaxGrid x kMaxTrials

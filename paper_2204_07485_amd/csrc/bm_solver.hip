@@ -867,16 +867,18 @@ __device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& 
   const int k = a.k;
   const int kd = k * d;
   const int na = L.misc[0];
-  double* ring = a.sums + static_cast<size_t>(pass % 3) * kd;
-  int32_t* cring = a.cnt + static_cast<size_t>(pass % 3) * k;
+  // this workgroup's replica of ring slot (pass % 3)
+  const int rep = g % kReplicas;
+  double* ring = a.sums + (static_cast<size_t>(pass % 3) * kReplicas + rep) * kd;
+  int32_t* cring = a.cnt + (static_cast<size_t>(pass % 3) * kReplicas + rep) * k;
   double* sums_l = reinterpret_cast<double*>(L.B + pl.sums);
   int* cnt_l = reinterpret_cast<int*>(L.B + pl.cntl);
 
-  if (g == 0) {  // clear the ring slot the next pass accumulates into
-    double* nring = a.sums + static_cast<size_t>((pass + 1) % 3) * kd;
-    int32_t* ncring = a.cnt + static_cast<size_t>((pass + 1) % 3) * k;
-    for (int e = tid; e < kd; e += kBlock) nring[e] = 0.0;
-    for (int j = tid; j < k; j += kBlock) ncring[j] = 0;
+  if (g == 0) {  // clear the ring slot (all replicas) the next pass accumulates into
+    double* nring = a.sums + static_cast<size_t>((pass + 1) % 3) * kReplicas * kd;
+    int32_t* ncring = a.cnt + static_cast<size_t>((pass + 1) % 3) * kReplicas * k;
+    for (int e = tid; e < kReplicas * kd; e += kBlock) nring[e] = 0.0;
+    for (int j = tid; j < kReplicas * k; j += kBlock) ncring[j] = 0;
   }
   const int ld = a.sums_in_lds ? sums_ld(d) : d;
   if (accumulate) {
@@ -931,20 +933,30 @@ __device__ __forceinline__ double gather_pass(const SolverArgs& a, const LdsPlan
   double v = 0.0;
   if (g0 < G) v = part[g0];
   if (g0 + 1 < G) v += part[g0 + 1];
-  const double* ring = a.sums + static_cast<size_t>(used % 3) * kd;
-  const int32_t* cring = a.cnt + static_cast<size_t>(used % 3) * k;
+  const double* ring = a.sums + static_cast<size_t>(used % 3) * kReplicas * kd;
+  const int32_t* cring = a.cnt + static_cast<size_t>(used % 3) * kReplicas * k;
   int* cnt_l = reinterpret_cast<int*>(L.B + pl.cntl);
   if (a.sums_in_lds) {
     double* stage = reinterpret_cast<double*>(L.B + pl.sums);
     const int d = a.d;
     const int ld = sums_ld(d);
-#pragma unroll 4
     for (int e = tid; e < kd; e += kBlock) {
+      double r[kReplicas];
+#pragma unroll
+      for (int q = 0; q < kReplicas; ++q) r[q] = ring[static_cast<size_t>(q) * kd + e];
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < kReplicas; ++q) v += r[q];  // fixed order
       const int j = e / d;
-      stage[j * ld + (e - j * d)] = ring[e];
+      stage[j * ld + (e - j * d)] = v;
     }
   }
-  for (int j = tid; j < k; j += kBlock) cnt_l[j] = cring[j];
+  for (int j = tid; j < k; j += kBlock) {
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < kReplicas; ++q) c += cring[static_cast<size_t>(q) * k + j];
+    cnt_l[j] = c;
+  }
   return block_sum_f64<kBlock>(v, L.tmpd);
 }
 
@@ -961,7 +973,7 @@ __device__ __forceinline__ double update_centroids(const SolverArgs& a, const Ld
   const int tid = threadIdx.x;
   const int d = a.d;
   const int k = a.k;
-  const double* ring = a.sums + static_cast<size_t>(used % 3) * k * d;
+  const double* ring = a.sums + static_cast<size_t>(used % 3) * kReplicas * k * d;
   const double* c_old = a.c64_in_lds ? L.c64 : a.c64 + static_cast<size_t>((it + 1) & 1) * k * d;
   double* c_new = a.c64_in_lds ? L.c64 : a.c64 + static_cast<size_t>(it & 1) * k * d;
   const int* cnt_l = reinterpret_cast<const int*>(L.B + pl.cntl);
@@ -999,7 +1011,10 @@ __device__ __forceinline__ double update_centroids(const SolverArgs& a, const Ld
       for (int tdim = 0; tdim < d; ++tdim) moved = __dadd_rn(moved, dsq[j * ld + tdim]);
     } else {
       for (int tdim = 0; tdim < d; ++tdim) {
-        const double mean = ring[j * d + tdim] / static_cast<double>(c);
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < kReplicas; ++q) sum += ring[static_cast<size_t>(q) * k * d + j * d + tdim];
+        const double mean = sum / static_cast<double>(c);
         const double diff = mean - c_old[j * d + tdim];
         moved = __dadd_rn(moved, __dmul_rn(diff, diff));
         c_new[j * d + tdim] = mean;
