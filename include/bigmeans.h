@@ -56,7 +56,7 @@ enum {
 enum { BM_F32 = 0, BM_BF16 = 1 };               /* element type of X       */
 enum { BM_STOP_SHIFT = 0, BM_STOP_REL_OBJ = 1 }; /* Lloyd stop rule         */
 enum { BM_CMP_FOPT = 0, BM_CMP_RESAMPLE = 1 };   /* keep-the-best reference */
-enum { BM_PREC_FP32 = 0 };                       /* distance arithmetic     */
+enum { BM_PREC_FP32 = 0, BM_PREC_BF16_MFMA = 1 }; /* distance arithmetic    */
 
 #define BM_ABI_VERSION 1
 
@@ -76,7 +76,15 @@ typedef struct bm_options {
   int32_t compare_rule;   /* BM_CMP_FOPT: replace the incumbent when f(C'',P) <   */
                           /* f_opt (Alg. 1); BM_CMP_RESAMPLE: when f(C'',P) <     */
                           /* f(C,P) of the incumbent on the new sample (Sec. 3.2) */
-  int32_t precision;      /* BM_PREC_FP32                                         */
+  int32_t precision;      /* BM_PREC_FP32 (default): FP32 direct differences.     */
+                          /* BM_PREC_BF16_MFMA (X must be BM_BF16): the full-data */
+                          /* assignment (kmeans_assign, the final pass of         */
+                          /* bigmeans_fit) takes x.c on the matrix cores with the */
+                          /* centroids split into two BF16 parts, and recomputes  */
+                          /* on the FP32 path every point whose two best          */
+                          /* candidates are within a proven error bound, so the   */
+                          /* labels equal BM_PREC_FP32's; needs d <= 256, k <= 128 */
+                          /* and the split centroids in LDS (else BM_ENOTSUP)     */
   void* stream;           /* hipStream_t to run on; NULL = null stream            */
   int32_t grid;           /* workgroups of the cooperative solver; 0 = automatic  */
   int32_t t_start;        /* index of the first sample (resume); default 0        */
@@ -109,6 +117,8 @@ typedef struct bm_stats {
   double ms_lloyd_pass;   /* ... of which assignment passes (incl. their barrier) */
   double ms_lloyd_post;   /* ... of which reading the reductions + updating        */
   double ms_lloyd_wait;   /* ... of which waiting in the assignment-pass barrier  */
+  int64_t rechecked;      /* final pass, BM_PREC_BF16_MFMA: points recomputed on  */
+                          /* the FP32 path (near-ties)                            */
 } bm_stats;
 
 /* Fill *opt with defaults (struct_size set).  Returns BM_EINVAL on NULL. */

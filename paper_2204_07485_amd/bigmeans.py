@@ -18,7 +18,7 @@ BM_OK, BM_EINVAL, BM_ENOMEM, BM_EDEVICE, BM_ENOTSUP, BM_ECANCELLED = 0, -1, -2, 
 BM_F32, BM_BF16 = 0, 1
 BM_STOP_SHIFT, BM_STOP_REL_OBJ = 0, 1
 BM_CMP_FOPT, BM_CMP_RESAMPLE = 0, 1
-BM_PREC_FP32 = 0
+BM_PREC_FP32, BM_PREC_BF16_MFMA = 0, 1
 
 FUNCTIONS = ["bm_default_options", "bm_last_error", "bm_release_scratch", "bm_abi_version",
              "bigmeans_fit", "kmeans_assign", "kmeanspp_seed", "kmeans_lloyd",
@@ -50,7 +50,8 @@ class Stats(ct.Structure):
                 ("ms_solver", ct.c_double), ("ms_final", ct.c_double),
                 ("ms_sampling", ct.c_double), ("ms_seeding", ct.c_double),
                 ("ms_lloyd", ct.c_double), ("ms_lloyd_pass", ct.c_double),
-                ("ms_lloyd_post", ct.c_double), ("ms_lloyd_wait", ct.c_double)]
+                ("ms_lloyd_post", ct.c_double), ("ms_lloyd_wait", ct.c_double),
+                ("rechecked", ct.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}
@@ -87,6 +88,8 @@ def load(path=LIB_PATH):
     L.kmeans_lloyd.restype = I32
     L.bm_sample_indices.argtypes = [I64, I64, U64, I32, P, P]
     L.bm_sample_indices.restype = I32
+    L.bm_debug_rechecked.argtypes = []
+    L.bm_debug_rechecked.restype = I64
     _LIB = L
     return L
 
@@ -227,6 +230,12 @@ def sample_indices(n, s, seed, t, device="cuda", **opts):
     rc = L.bm_sample_indices(n, s, ct.c_uint64(seed), t, ct.c_void_p(idx.data_ptr()), ct.byref(o))
     _check(rc)
     return idx
+
+
+def last_rechecked():
+    """Points the last BF16-MFMA kmeans_assign on this thread recomputed on the
+    FP32 path (near ties)."""
+    return int(load().bm_debug_rechecked())
 
 
 def release_scratch():

@@ -15,6 +15,7 @@ namespace bm {
 
 static thread_local char g_err[512] = "";
 static thread_local int64_t g_last_counters[kNumCounters];
+static thread_local int64_t g_last_rechecked = 0;
 
 bm_status set_error(bm_status code, const char* fmt, ...) {
   va_list ap;
@@ -126,7 +127,10 @@ static bm_status resolve(const bm_options* in, bm_options* out) {
     return set_error(BM_EINVAL, "n_local_trials must be in [1, %d]", kMaxTrials);
   if (out->compare_rule != BM_CMP_FOPT && out->compare_rule != BM_CMP_RESAMPLE)
     return set_error(BM_EINVAL, "compare_rule %d", out->compare_rule);
-  if (out->precision != BM_PREC_FP32) return set_error(BM_ENOTSUP, "precision %d", out->precision);
+  if (out->precision != BM_PREC_FP32 && out->precision != BM_PREC_BF16_MFMA)
+    return set_error(BM_EINVAL, "precision %d", out->precision);
+  if (out->precision == BM_PREC_BF16_MFMA && out->x_dtype != BM_BF16)
+    return set_error(BM_EINVAL, "BM_PREC_BF16_MFMA needs BF16 points (x_dtype = BM_BF16)");
   if (out->grid < 0 || out->grid > kMaxGrid) return set_error(BM_EINVAL, "grid %d", out->grid);
   if (out->t_start < 0) return set_error(BM_EINVAL, "t_start must be >= 0");
   return BM_OK;
@@ -190,6 +194,7 @@ struct SolverBuffers {
   double* partial = nullptr;      // final assignment pass: per-workgroup objective
   unsigned int* done = nullptr;   //   arrival counter of its last-workgroup reduction
   double* sse_dev = nullptr;      //   the objective
+  unsigned long long* rechecked = nullptr;  //   points recomputed on the FP32 path (MFMA form)
   size_t bytes = 0;
   size_t ctrl_bytes = 0;  // prefix cleared before each launch
 };
@@ -237,6 +242,7 @@ static void layout_solver(char* base, int64_t n, int64_t s, int d, int k, int T,
   b->partial = L.take<double>(final_grid > 0 ? final_grid : 1);
   b->done = L.take<unsigned int>(1);
   b->sse_dev = L.take<double>(1);
+  b->rechecked = L.take<unsigned long long>(1);
   b->bytes = L.off + 256;
 }
 
@@ -252,7 +258,10 @@ static bm_status prepare_solver(hipStream_t stream, int64_t n, int64_t s, int d,
   b->a = keep;
   layout_solver(base, n, s, d, k, T, cand_cap, own_P, own_idx, own_labels, own_inc, final_grid, b);
   BM_HIP(hipMemsetAsync(base, 0, b->ctrl_bytes, stream));
-  if (final_grid > 0) BM_HIP(hipMemsetAsync(b->done, 0, sizeof(unsigned int), stream));
+  if (final_grid > 0) {
+    BM_HIP(hipMemsetAsync(b->done, 0, sizeof(unsigned int), stream));
+    BM_HIP(hipMemsetAsync(b->rechecked, 0, sizeof(unsigned long long), stream));
+  }
   return BM_OK;
 }
 
@@ -313,6 +322,10 @@ int32_t bm_debug_counters(int64_t* out, int32_t n) {
   return BM_OK;
 }
 
+// Points the last BM_PREC_BF16_MFMA kmeans_assign on this thread recomputed
+// on the FP32 path (diagnostics; not declared in the public header).
+int64_t bm_debug_rechecked(void) { return g_last_rechecked; }
+
 bm_status bm_release_scratch(void) {
   std::lock_guard<std::mutex> lock(g_mu);
   (void)hipDeviceSynchronize();
@@ -343,7 +356,9 @@ bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s
   if ((st = plan_solver(d, k, s, n, o.grid, &sp)) != BM_OK) return st;
 
   const bool final_pass = sse || labels;
-  const int final_grid = final_pass ? assign_grid(n) : 0;
+  const bool final_mfma = final_pass && o.precision == BM_PREC_BF16_MFMA;
+  int final_grid = final_pass ? assign_grid(n) : 0;
+  if (final_mfma && (st = plan_assign_mfma(X, n, d, k, &final_grid)) != BM_OK) return st;
   SolverBuffers b;
   memset(&b.a, 0, sizeof b.a);
   if ((st = prepare_solver(stream, n, s, d, k, n_samples, sp.cand_cap, true, true, true, true,
@@ -397,7 +412,10 @@ bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s
   // final assignment (Alg. 1 last step) over all of X
   double sse_host = 0.0;
   bm_status fst = BM_OK;
-  if (final_pass) {
+  if (final_mfma) {
+    fst = launch_assign_mfma(static_cast<const uint16_t*>(X), n, d, a.Cinc, a.deg_inc, k, labels,
+                             nullptr, b.partial, b.done, b.sse_dev, b.rechecked, final_grid, stream);
+  } else if (final_pass) {
     fst = launch_assign(X, a.x_bf16, n, d, a.Cinc, a.deg_inc, k, labels, nullptr, b.partial,
                         b.done, b.sse_dev, final_grid, stream);
   }
@@ -410,6 +428,9 @@ bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s
   double fopt = 0.0;
   BM_HIP(hipMemcpyAsync(counters, a.counters, sizeof counters, hipMemcpyDeviceToHost, stream));
   BM_HIP(hipMemcpyAsync(&fopt, a.f_opt, sizeof fopt, hipMemcpyDeviceToHost, stream));
+  unsigned long long nrecheck = 0;
+  if (final_mfma)
+    BM_HIP(hipMemcpyAsync(&nrecheck, b.rechecked, sizeof nrecheck, hipMemcpyDeviceToHost, stream));
   if (degenerate)
     BM_HIP(hipMemcpyAsync(degenerate, a.deg_inc, size_t(k), hipMemcpyDeviceToHost, stream));
   if (o.sample_f)
@@ -434,6 +455,7 @@ bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s
     stats->f_opt = fopt;
     stats->ms_solver = ms_solver;
     stats->ms_final = ms_final;
+    stats->rechecked = static_cast<int64_t>(nrecheck);
     int dev = 0, khz = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0) {
@@ -465,12 +487,15 @@ bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, con
   }
   if (padded_dim(d) < 0) return set_error(BM_ENOTSUP, "d = %d exceeds the limit of 256", d);
   hipStream_t stream = static_cast<hipStream_t>(o.stream);
+  const bool mfma = o.precision == BM_PREC_BF16_MFMA;
   std::lock_guard<std::mutex> lock(g_mu);
-  const int grid = assign_grid(n);
+  int grid = assign_grid(n);
+  if (mfma && (st = plan_assign_mfma(X, n, d, k, &grid)) != BM_OK) return st;
   uint8_t* deg_p = nullptr;
   double* partial_p = nullptr;
   unsigned int* done_p = nullptr;
   double* sse_p = nullptr;
+  unsigned long long* rechecked_p = nullptr;
   char* base = nullptr;
   for (int round = 0; round < 2; ++round) {
     Layout L;
@@ -479,6 +504,7 @@ bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, con
     partial_p = L.take<double>(grid);
     done_p = L.take<unsigned int>(1);
     sse_p = L.take<double>(1);
+    rechecked_p = L.take<unsigned long long>(1);
     if (round == 0) {
       bm_status st2 = BM_OK;
       base = static_cast<char*>(scratch_get(L.off + 256, stream, &st2));
@@ -487,12 +513,22 @@ bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, con
   }
   if (deg) BM_HIP(hipMemcpyAsync(deg_p, deg, size_t(k), hipMemcpyHostToDevice, stream));
   BM_HIP(hipMemsetAsync(done_p, 0, sizeof(unsigned int), stream));
-  st = launch_assign(X, o.x_dtype == BM_BF16, n, d, C, deg ? deg_p : nullptr, k, labels, min_d2,
-                     partial_p, done_p, sse_p, grid, stream);
+  if (mfma) {
+    BM_HIP(hipMemsetAsync(rechecked_p, 0, sizeof(unsigned long long), stream));
+    st = launch_assign_mfma(static_cast<const uint16_t*>(X), n, d, C, deg ? deg_p : nullptr, k,
+                            labels, min_d2, partial_p, done_p, sse_p, rechecked_p, grid, stream);
+  } else {
+    st = launch_assign(X, o.x_dtype == BM_BF16, n, d, C, deg ? deg_p : nullptr, k, labels, min_d2,
+                       partial_p, done_p, sse_p, grid, stream);
+  }
   if (st != BM_OK) return st;
   double v = 0.0;
+  unsigned long long nrecheck = 0;
   BM_HIP(hipMemcpyAsync(&v, sse_p, sizeof v, hipMemcpyDeviceToHost, stream));
+  if (mfma)
+    BM_HIP(hipMemcpyAsync(&nrecheck, rechecked_p, sizeof nrecheck, hipMemcpyDeviceToHost, stream));
   BM_HIP(hipStreamSynchronize(stream));
+  g_last_rechecked = static_cast<int64_t>(nrecheck);
   if (sse) *sse = v;
   return BM_OK;
 }

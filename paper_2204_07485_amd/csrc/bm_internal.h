@@ -128,4 +128,13 @@ bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float
                         hipStream_t stream);
 int assign_grid(int64_t n);
 
+// BF16 matrix-core assignment (bm_assign_mfma.hip): plan checks the shape and
+// picks the grid; the launch writes the same outputs as launch_assign and
+// adds the number of points it recomputed on the FP32 path to *rechecked.
+bm_status plan_assign_mfma(const void* X, int64_t n, int d, int k, int* grid);
+bm_status launch_assign_mfma(const uint16_t* X, int64_t n, int d, const float* C,
+                             const uint8_t* deg_dev, int k, int32_t* labels, float* min_d2,
+                             double* partial, unsigned int* done, double* sse_dev,
+                             unsigned long long* rechecked, int grid, hipStream_t stream);
+
 }  // namespace bm
