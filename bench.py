@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=12,
                     help="samples the CPU oracle runs for its bounded baseline")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the BF16 workload's mixed-precision (MFMA) comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a plain 1 GiB device copy three times (a known "
                          "amount of HBM traffic for scaling profiler byte counters)")
@@ -91,6 +93,58 @@ def cpu_baseline(X, W, n_cpu_samples):
     return {"value": ms, "unit": "ms", "cores": 1, "kind": "oracle",
             "sample": f"first {n_cpu_samples} of {W.n_samples} samples ({t_samples:.1f} s) "
                       f"scaled to {W.n_samples}, plus one full final pass ({t_final:.1f} s)"}
+
+
+def mixed_precision(reps=5):
+    """The BF16 workload (5,000,000 x 128 BF16, 100 components + 10% outliers,
+    k=100, s=200,000, 30 samples, seed 4): one full fit per distance
+    arithmetic (the final pass differs), then the final assignment pass alone
+    timed with HIP events for both forms on the fit's centroids."""
+    import numpy as np
+    import torch
+
+    from paper_2204_07485_amd import bigmeans, synth
+    W = synth.BF16
+    H = synth.make_bf16()
+    Hd = torch.from_numpy(H.view(np.int16)).to("cuda:0")
+    del H
+    kw = dict(max_iter=300, tol=1e-4, stop_rule=bigmeans.BM_STOP_REL_OBJ, n_local_trials=3)
+    fits = {}
+    for name, prec in (("fp32", bigmeans.BM_PREC_FP32), ("bf16_mfma", bigmeans.BM_PREC_BF16_MFMA)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = bigmeans.bigmeans_fit(Hd, W.k, W.s, W.n_samples, W.seed, precision=prec, **kw)
+        fits[name] = (r, (time.perf_counter() - t0) * 1e3)
+    C, deg = fits["bf16_mfma"][0]["centroids"], fits["bf16_mfma"][0]["degenerate"]
+    ms = {}
+    out = {}
+    for name, prec in (("fp32", bigmeans.BM_PREC_FP32), ("bf16_mfma", bigmeans.BM_PREC_BF16_MFMA)):
+        vals = []
+        for _ in range(reps):
+            lab, _, sse = bigmeans.kmeans_assign(Hd, C, deg, precision=prec)
+            vals.append(bigmeans.last_assign_ms())
+        ms[name] = statistics.median(vals)
+        out[name] = (lab.cpu().numpy(), sse, bigmeans.last_rechecked() if prec else 0)
+    n, d, k = W.n, W.d, W.k
+    algo_bytes = n * d * 2 + n * 4
+    kp = 16 * ((k + 15) // 16)
+    gbs = algo_bytes / (ms["bf16_mfma"] * 1e-3) / 1e9
+    return {
+        "workload": "bf16: 5,000,000 x 128 BF16 Gaussian mixture (100 components, sigma "
+                    "U[0.5,2], 10% uniform outliers), k=100, s=200,000, 30 samples, seed 4",
+        "fit_ms": {k_: v[1] for k_, v in fits.items()},
+        "fit_sse": {k_: v[0]["sse"] for k_, v in fits.items()},
+        "final_pass_ms": ms,
+        "final_pass_speedup": ms["fp32"] / ms["bf16_mfma"],
+        "labels_equal": bool((out["fp32"][0] == out["bf16_mfma"][0]).all()),
+        "sse_rel_diff": abs(out["fp32"][1] - out["bf16_mfma"][1]) / out["fp32"][1],
+        "rechecked": int(out["bf16_mfma"][2]),
+        "roofline": {"bound": "hbm", "kernel": "assign_mfma_kernel<4,true>", "achieved": gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes": algo_bytes,
+                     "mfma_tflops": 2 * 2 * n * kp * d / (ms["bf16_mfma"] * 1e-3) / 1e12,
+                     "fp32_path_tflops": 2 * n * k * d / (ms["fp32"] * 1e-3) / 1e12},
+    }
 
 
 def main():
@@ -198,6 +252,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if not args.no_mixed:
+        print("mixed precision: BF16 workload ...", file=sys.stderr, flush=True)
+        line["mixed_precision"] = mixed_precision()
     if not args.no_cpu_baseline:
         print("cpu baseline (oracle, 1 thread) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(X, W, args.cpu_samples)

@@ -90,6 +90,8 @@ def load(path=LIB_PATH):
     L.bm_sample_indices.restype = I32
     L.bm_debug_rechecked.argtypes = []
     L.bm_debug_rechecked.restype = I64
+    L.bm_debug_assign_ms.argtypes = []
+    L.bm_debug_assign_ms.restype = ct.c_double
     _LIB = L
     return L
 
@@ -236,6 +238,11 @@ def last_rechecked():
     """Points the last BF16-MFMA kmeans_assign on this thread recomputed on the
     FP32 path (near ties)."""
     return int(load().bm_debug_rechecked())
+
+
+def last_assign_ms():
+    """Device time of the last kmeans_assign's kernel on this thread (ms)."""
+    return float(load().bm_debug_assign_ms())
 
 
 def release_scratch():

@@ -16,6 +16,7 @@ namespace bm {
 static thread_local char g_err[512] = "";
 static thread_local int64_t g_last_counters[kNumCounters];
 static thread_local int64_t g_last_rechecked = 0;
+static thread_local double g_last_assign_ms = 0.0;
 
 bm_status set_error(bm_status code, const char* fmt, ...) {
   va_list ap;
@@ -326,6 +327,11 @@ int32_t bm_debug_counters(int64_t* out, int32_t n) {
 // on the FP32 path (diagnostics; not declared in the public header).
 int64_t bm_debug_rechecked(void) { return g_last_rechecked; }
 
+// Device time (HIP events on the call's stream) of the assignment kernel of
+// the last kmeans_assign on this thread, in ms (diagnostics; not declared in
+// the public header).
+double bm_debug_assign_ms(void) { return g_last_assign_ms; }
+
 bm_status bm_release_scratch(void) {
   std::lock_guard<std::mutex> lock(g_mu);
   (void)hipDeviceSynchronize();
@@ -513,21 +519,33 @@ bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, con
   }
   if (deg) BM_HIP(hipMemcpyAsync(deg_p, deg, size_t(k), hipMemcpyHostToDevice, stream));
   BM_HIP(hipMemsetAsync(done_p, 0, sizeof(unsigned int), stream));
+  if (mfma) BM_HIP(hipMemsetAsync(rechecked_p, 0, sizeof(unsigned long long), stream));
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (auto& e : ev) BM_HIP(hipEventCreate(&e));
+  BM_HIP(hipEventRecord(ev[0], stream));
   if (mfma) {
-    BM_HIP(hipMemsetAsync(rechecked_p, 0, sizeof(unsigned long long), stream));
     st = launch_assign_mfma(static_cast<const uint16_t*>(X), n, d, C, deg ? deg_p : nullptr, k,
                             labels, min_d2, partial_p, done_p, sse_p, rechecked_p, grid, stream);
   } else {
     st = launch_assign(X, o.x_dtype == BM_BF16, n, d, C, deg ? deg_p : nullptr, k, labels, min_d2,
                        partial_p, done_p, sse_p, grid, stream);
   }
-  if (st != BM_OK) return st;
+  if (st == BM_OK && hipEventRecord(ev[1], stream) != hipSuccess)
+    st = set_error(BM_EDEVICE, "hipEventRecord failed");
+  if (st != BM_OK) {
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return st;
+  }
   double v = 0.0;
   unsigned long long nrecheck = 0;
   BM_HIP(hipMemcpyAsync(&v, sse_p, sizeof v, hipMemcpyDeviceToHost, stream));
   if (mfma)
     BM_HIP(hipMemcpyAsync(&nrecheck, rechecked_p, sizeof nrecheck, hipMemcpyDeviceToHost, stream));
-  BM_HIP(hipStreamSynchronize(stream));
+  const hipError_t sync = hipStreamSynchronize(stream);
+  g_last_assign_ms = sync == hipSuccess ? elapsed_ms(ev[0], ev[1]) : 0.0;
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (sync != hipSuccess)
+    return set_error(BM_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(sync));
   g_last_rechecked = static_cast<int64_t>(nrecheck);
   if (sse) *sse = v;
   return BM_OK;

@@ -331,9 +331,10 @@ __global__ void __launch_bounds__((block_for<KS, VEC>()))
           // keep b1 <= b2 the two smallest; the median of three is the new
           // runner-up, and j1 moves only on a strict improvement (ascending m)
           const float e = __builtin_fmaf(-2.0f, acc[nt][q], cnq[q]);
-          j1[nt] = e < b1[nt] ? m : j1[nt];
+          const bool lt = e < b1[nt];
+          j1[nt] = lt ? m : j1[nt];
           b2[nt] = __builtin_amdgcn_fmed3f(b1[nt], b2[nt], e);
-          b1[nt] = fminf(b1[nt], e);
+          b1[nt] = lt ? e : b1[nt];
         }
       }
     }
