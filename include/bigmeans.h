@@ -212,6 +212,42 @@ bm_status kmeans_lloyd(const float* P, int64_t s, int32_t d, int32_t k, float* C
 bm_status bm_sample_indices(int64_t n, int64_t s, uint64_t seed, int32_t t, int32_t* idx,
                             const bm_options* opt);
 
+/*
+ * bm_gather_rows -- P[r] = X[idx[r]] for r < s, widened to FP32 (the sample
+ * matrix of Alg. 1 built from a sample's indices, Sec. 3.1).
+ *   X    device n x d (FP32, or BF16 per opt->x_dtype).
+ *   idx  device s int32 row indices, each in [0, n) (else BM_EINVAL, P partly written).
+ *   P    device s x d FP32 out.
+ */
+bm_status bm_gather_rows(const void* X, int64_t n, int32_t d, const int32_t* idx, int64_t s,
+                         float* P, const bm_options* opt);
+
+/*
+ * kmeans_lloyd_batched -- kmeans_lloyd (K-means, Sec. 2) on n_solves
+ * independent problems at once, as the parallel workers of Big-means run it
+ * on their own samples (Sec. 3.6): every round assigns all rows of every
+ * unfinished problem and updates its centroids, with each problem's stop rule,
+ * tolerance and cap from opt, and stops a problem exactly where kmeans_lloyd
+ * would.  One graph launch per round on an internal stream ordered after
+ * opt->stream.
+ *   P        device, the problems' rows concatenated: problem j owns
+ *            s[j] rows starting after those of problems 0 .. j-1; FP32, d wide.
+ *   s, k     host n_solves each: rows and centroids per problem, 1 <= k <= s.
+ *   C        device, the problems' k[j] x d centroids concatenated, in/out.
+ *   deg      host, sum(k) bytes, in/out (1 = degenerate, as kmeans_lloyd).
+ *   labels   device, sum(s) int32 out (nearest centroid within the problem,
+ *            for the returned centroids), or NULL.
+ *   f        host n_solves out: objective of each returned C on its rows (FP64), or NULL.
+ *   passes   host n_solves out: assignment passes per problem, or NULL.
+ * The row tile per work item is tuned once per shape (timed) and cached.
+ * Errors: BM_EINVAL for bad sizes or pointers, BM_ENOTSUP when d > 256 or
+ * the largest k x d does not fit the workgroup's LDS, BM_EDEVICE on a HIP
+ * failure.
+ */
+bm_status kmeans_lloyd_batched(int32_t n_solves, const float* P, int32_t d, const int64_t* s,
+                               const int32_t* k, float* C, uint8_t* deg, const bm_options* opt,
+                               int32_t* labels, double* f, int32_t* passes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,7 @@ BM_PREC_FP32, BM_PREC_BF16_MFMA = 0, 1
 
 FUNCTIONS = ["bm_default_options", "bm_last_error", "bm_release_scratch", "bm_abi_version",
              "bigmeans_fit", "kmeans_assign", "kmeanspp_seed", "kmeans_lloyd",
-             "bm_sample_indices"]
+             "bm_sample_indices", "bm_gather_rows", "kmeans_lloyd_batched"]
 
 
 class BigmeansError(RuntimeError):
@@ -88,6 +88,12 @@ def load(path=LIB_PATH):
     L.kmeans_lloyd.restype = I32
     L.bm_sample_indices.argtypes = [I64, I64, U64, I32, P, P]
     L.bm_sample_indices.restype = I32
+    L.bm_gather_rows.argtypes = [P, I64, I32, P, I64, P, P]
+    L.bm_gather_rows.restype = I32
+    L.kmeans_lloyd_batched.argtypes = [I32, P, I32, P, P, P, P, P, P, P, P]
+    L.kmeans_lloyd_batched.restype = I32
+    L.bm_debug_batch_info.argtypes = [P, P]
+    L.bm_debug_batch_info.restype = I32
     L.bm_debug_rechecked.argtypes = []
     L.bm_debug_rechecked.restype = I64
     L.bm_debug_assign_ms.argtypes = []
@@ -232,6 +238,68 @@ def sample_indices(n, s, seed, t, device="cuda", **opts):
     rc = L.bm_sample_indices(n, s, ct.c_uint64(seed), t, ct.c_void_p(idx.data_ptr()), ct.byref(o))
     _check(rc)
     return idx
+
+
+def gather_rows(X, idx, out=None, **opts):
+    """P[r] = X[idx[r]] as FP32 (device tensors)."""
+    L = load()
+    n, d = X.shape
+    xp, xdt = _x_ptr(X)
+    o = options(x_dtype=xdt, **opts)
+    s = idx.shape[0]
+    P = out if out is not None else torch.empty((s, d), dtype=torch.float32, device=X.device)
+    _check(L.bm_gather_rows(xp, n, d, _dev_ptr(idx, torch.int32, "idx"), s,
+                            _dev_ptr(P, torch.float32, "P"), ct.byref(o)))
+    return P
+
+
+def kmeans_lloyd_batched(P, s, k, C, deg, want_labels=True, **opts):
+    """Lloyd on many problems at once.  P: device (sum(s), d) FP32 rows of the
+    problems in order; s, k: per-problem rows and centroids; C: device
+    (sum(k), d) FP32 start centroids, updated in place; deg: sum(k) flags.
+    Returns (deg, labels or None, f per problem, passes per problem, info)."""
+    L = load()
+    n_solves = len(s)
+    d = P.shape[1]
+    s_arr = np.ascontiguousarray(s, dtype=np.int64)
+    k_arr = np.ascontiguousarray(k, dtype=np.int32)
+    dg = np.array(deg, dtype=np.uint8, copy=True)
+    o = options(**opts)
+    labels = torch.empty(int(s_arr.sum()), dtype=torch.int32, device=P.device) if want_labels else None
+    f = np.zeros(n_solves, dtype=np.float64)
+    passes = np.zeros(n_solves, dtype=np.int32)
+    _check(L.kmeans_lloyd_batched(n_solves, _dev_ptr(P, torch.float32, "P"), d,
+                                  s_arr.ctypes.data_as(ct.c_void_p), k_arr.ctypes.data_as(ct.c_void_p),
+                                  _dev_ptr(C, torch.float32, "C"), dg.ctypes.data_as(ct.c_void_p),
+                                  ct.byref(o), None if labels is None else ct.c_void_p(labels.data_ptr()),
+                                  f.ctypes.data_as(ct.c_void_p), passes.ctypes.data_as(ct.c_void_p)))
+    rounds, tile = ct.c_int32(0), ct.c_int32(0)
+    L.bm_debug_batch_info(ct.byref(rounds), ct.byref(tile))
+    return dg, labels, f, passes, {"rounds": rounds.value, "tile_rows": tile.value}
+
+
+def prepare_batch(X, solves, n_local_trials=3, **opts):
+    """Start problems for kmeans_lloyd_batched: for solve j = (s_j, k_j, seed_j),
+    the sample of sample index 0 under seed_j (bm_sample_indices), its rows
+    (bm_gather_rows) and k_j K-means++ centres on it (kmeanspp_seed), as the
+    first sample of a Big-means run with that seed.  Returns (P, s, k, C, deg)."""
+    s = np.array([sj for sj, _, _ in solves], dtype=np.int64)
+    k = np.array([kj for _, kj, _ in solves], dtype=np.int32)
+    d = X.shape[1]
+    P = torch.empty((int(s.sum()), d), dtype=torch.float32, device=X.device)
+    C = torch.empty((int(k.sum()), d), dtype=torch.float32, device=X.device)
+    deg = np.ones(int(k.sum()), dtype=np.uint8)
+    r = c = 0
+    for sj, kj, seed in solves:
+        idx = sample_indices(X.shape[0], sj, seed, 0, device=X.device)
+        Pj = P[r:r + sj]
+        gather_rows(X, idx, out=Pj, **opts)
+        Cj = C[c:c + kj]
+        deg[c:c + kj] = kmeanspp_seed(Pj, Cj, np.ones(kj, np.uint8), seed, 0,
+                                      n_local_trials=n_local_trials, **opts)
+        r += sj
+        c += kj
+    return P, s, k, C, deg
 
 
 def last_rechecked():

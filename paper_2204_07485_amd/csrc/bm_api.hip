@@ -4,7 +4,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
+#include <vector>
 
 #include "bm_internal.h"
 
@@ -17,6 +19,8 @@ static thread_local char g_err[512] = "";
 static thread_local int64_t g_last_counters[kNumCounters];
 static thread_local int64_t g_last_rechecked = 0;
 static thread_local double g_last_assign_ms = 0.0;
+static thread_local int32_t g_last_batch_rounds = 0;
+static thread_local int32_t g_last_batch_tile = 0;
 
 bm_status set_error(bm_status code, const char* fmt, ...) {
   va_list ap;
@@ -294,6 +298,36 @@ static float elapsed_ms(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
   return ms;
+}
+
+// ---------------------------------------------------------------------------
+// batched Lloyd: host-side plan
+
+struct BatchShape {
+  int d, kmax, n_solves;
+  int64_t rows;
+  bool operator<(const BatchShape& o) const {
+    if (d != o.d) return d < o.d;
+    if (kmax != o.kmax) return kmax < o.kmax;
+    if (n_solves != o.n_solves) return n_solves < o.n_solves;
+    return rows < o.rows;
+  }
+};
+static std::map<BatchShape, int> g_tile_cache;  // tuned rows per tile (under g_mu)
+
+// Work list for a tile size: tile -> solve, and each solve's first tile.
+static int build_tiles(const std::vector<int64_t>& s, int tile_rows, std::vector<int32_t>* tile_solve,
+                       std::vector<int32_t>* tile0, std::vector<int32_t>* ntiles) {
+  tile_solve->clear();
+  tile0->assign(s.size(), 0);
+  ntiles->assign(s.size(), 0);
+  for (size_t j = 0; j < s.size(); ++j) {
+    const int64_t nt = (s[j] + tile_rows - 1) / tile_rows;
+    (*tile0)[j] = static_cast<int32_t>(tile_solve->size());
+    (*ntiles)[j] = static_cast<int32_t>(nt);
+    for (int64_t q = 0; q < nt; ++q) tile_solve->push_back(static_cast<int32_t>(j));
+  }
+  return static_cast<int>(tile_solve->size());
 }
 
 }  // namespace bm
@@ -670,6 +704,234 @@ bm_status bm_sample_indices(int64_t n, int64_t s, uint64_t seed, int32_t t, int3
   a.spin_limit = o.spin_limit ? o.spin_limit : kDefaultSpinLimit;
   if ((st = launch_solver(a, sp.grid, sp.lds, stream)) != BM_OK) return st;
   return check_solver_error(a, stream, nullptr);
+}
+
+bm_status bm_gather_rows(const void* X, int64_t n, int32_t d, const int32_t* idx, int64_t s,
+                         float* P, const bm_options* opt_in) {
+  clear_error();
+  bm_options o;
+  bm_status st = resolve(opt_in, &o);
+  if (st != BM_OK) return st;
+  if (n < 1 || n > 2147483647LL || d < 1 || s < 1)
+    return set_error(BM_EINVAL, "bad sizes n=%lld d=%d s=%lld", (long long)n, d, (long long)s);
+  if (!X || !idx || !P) return set_error(BM_EINVAL, "X, idx and P are required");
+  hipStream_t stream = static_cast<hipStream_t>(o.stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  int* bad = static_cast<int*>(scratch_get(256, stream, &st));
+  if (!bad) return st;
+  BM_HIP(hipMemsetAsync(bad, 0, sizeof(int), stream));
+  if ((st = launch_gather_rows(X, o.x_dtype == BM_BF16, n, d, idx, s, P, bad, stream)) != BM_OK)
+    return st;
+  int bad_h = 0;
+  BM_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+  BM_HIP(hipStreamSynchronize(stream));
+  if (bad_h) return set_error(BM_EINVAL, "an index is outside [0, n)");
+  return BM_OK;
+}
+
+bm_status kmeans_lloyd_batched(int32_t n_solves, const float* P, int32_t d, const int64_t* s,
+                               const int32_t* k, float* C, uint8_t* deg, const bm_options* opt_in,
+                               int32_t* labels, double* f, int32_t* passes) {
+  clear_error();
+  bm_options o;
+  bm_status st = resolve(opt_in, &o);
+  if (st != BM_OK) return st;
+  if (n_solves < 1 || d < 1) return set_error(BM_EINVAL, "need n_solves >= 1 and d >= 1");
+  if (!P || !s || !k || !C || !deg) return set_error(BM_EINVAL, "P, s, k, C and deg are required");
+  if (padded_dim(d) < 0) return set_error(BM_ENOTSUP, "d = %d exceeds the limit of 256", d);
+  std::vector<int64_t> sv_s(n_solves);
+  std::vector<BatchSolve> hs(n_solves);
+  int64_t rows = 0, ktot = 0;
+  int kmax = 0;
+  for (int j = 0; j < n_solves; ++j) {
+    if (s[j] < 1 || k[j] < 1 || k[j] > s[j])
+      return set_error(BM_EINVAL, "solve %d: need 1 <= k <= s (s=%lld, k=%d)", j, (long long)s[j], k[j]);
+    int active = 0;
+    for (int q = 0; q < k[j]; ++q) active += deg[ktot + q] ? 0 : 1;
+    if (!active) return set_error(BM_EINVAL, "solve %d: every centroid is degenerate", j);
+    sv_s[j] = s[j];
+    memset(&hs[j], 0, sizeof(BatchSolve));
+    hs[j].row0 = rows;
+    hs[j].s = s[j];
+    hs[j].c0 = static_cast<int32_t>(ktot);
+    hs[j].k = k[j];
+    hs[j].status = kSolveRunning;
+    hs[j].iter = 1;
+    hs[j].f_prev = __builtin_inf();
+    rows += s[j];
+    ktot += k[j];
+    kmax = k[j] > kmax ? k[j] : kmax;
+    if (rows > 2147483647LL || ktot > 2147483647LL)
+      return set_error(BM_EINVAL, "more than 2^31 rows or centroids in the batch");
+  }
+  size_t lds_max = 0;
+  if ((st = max_lds_per_block(&lds_max)) != BM_OK) return st;
+  const bool sums_lds = batch_assign_lds(d, kmax, true) + 1024 <= lds_max;
+  if (!sums_lds && batch_assign_lds(d, kmax, false) + 1024 > lds_max)
+    return set_error(BM_ENOTSUP, "k x d = %d x %d centroids do not fit in one workgroup's LDS", kmax, d);
+  hipStream_t user = static_cast<hipStream_t>(o.stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  int grid = 0;
+  if ((st = batch_assign_grid(d, kmax, sums_lds, &grid)) != BM_OK) return st;
+
+  // scratch: solve states, work list (sized for the smallest tile), tile
+  // objectives, FP64 sums, counts, FP64 means, flags, running counter
+  constexpr int kMinTile = 256;
+  int64_t max_tiles = 0;
+  for (int j = 0; j < n_solves; ++j) max_tiles += (s[j] + kMinTile - 1) / kMinTile;
+  BatchSolve* sv_d = nullptr;
+  int32_t* tiles_d = nullptr;
+  double* tile_f = nullptr;
+  double* sums = nullptr;
+  int32_t* cnt = nullptr;
+  double* c64 = nullptr;
+  uint8_t* deg_d = nullptr;
+  int* running = nullptr;
+  char* base = nullptr;
+  for (int round = 0; round < 2; ++round) {
+    Layout L;
+    L.base = base;
+    sv_d = L.take<BatchSolve>(n_solves);
+    tiles_d = L.take<int32_t>(max_tiles);
+    tile_f = L.take<double>(max_tiles);
+    sums = L.take<double>(ktot * d);
+    cnt = L.take<int32_t>(ktot);
+    c64 = L.take<double>(ktot * d);
+    deg_d = L.take<uint8_t>(ktot);
+    running = L.take<int>(1);
+    if (round == 0) {
+      base = static_cast<char*>(scratch_get(L.off + 256, user, &st));
+      if (!base) return st;
+    }
+  }
+  // an internal stream (capturable; default priority) ordered after the caller's
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (stream) (void)hipStreamDestroy(stream);
+  };
+  auto fail = [&](bm_status code) {
+    if (stream) (void)hipStreamSynchronize(stream);
+    cleanup();
+    return code;
+  };
+#define BM_HIPB(call)                                                                          \
+  do {                                                                                         \
+    const hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(set_error(BM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)));       \
+  } while (0)
+  BM_HIPB(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+  BM_HIPB(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+  BM_HIPB(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+  BM_HIPB(hipEventRecord(ev_in, user));
+  BM_HIPB(hipStreamWaitEvent(stream, ev_in, 0));
+  BM_HIPB(hipMemcpyAsync(deg_d, deg, static_cast<size_t>(ktot), hipMemcpyHostToDevice, stream));
+  BM_HIPB(hipMemsetAsync(sums, 0, sizeof(double) * ktot * d, stream));
+  BM_HIPB(hipMemsetAsync(cnt, 0, sizeof(int32_t) * ktot, stream));
+  if ((st = launch_batch_init(C, c64, ktot * d, stream)) != BM_OK) return fail(st);
+
+  // rows per tile: tuned once per shape by timing a dry assignment pass
+  std::vector<int32_t> tile_solve, tile0, ntiles;
+  const BatchShape shape{d, kmax, n_solves, rows};
+  int tile_rows = 0;
+  auto it_cache = g_tile_cache.find(shape);
+  auto upload = [&](int tr) -> bm_status {
+    const int nt = build_tiles(sv_s, tr, &tile_solve, &tile0, &ntiles);
+    for (int j = 0; j < n_solves; ++j) {
+      hs[j].tile0 = tile0[j];
+      hs[j].ntiles = ntiles[j];
+    }
+    BM_HIP(hipMemcpyAsync(tiles_d, tile_solve.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, stream));
+    BM_HIP(hipMemcpyAsync(sv_d, hs.data(), sizeof(BatchSolve) * n_solves, hipMemcpyHostToDevice, stream));
+    BM_HIP(hipStreamSynchronize(stream));  // the host vectors are reused
+    return BM_OK;
+  };
+  if (it_cache != g_tile_cache.end()) {
+    tile_rows = it_cache->second;
+  } else if (rows < 65536) {
+    tile_rows = 512;
+  } else {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    BM_HIPB(hipEventCreate(&t0));
+    BM_HIPB(hipEventCreate(&t1));
+    float best = 0.f;
+    for (int tr : {256, 512, 1024, 2048, 4096}) {
+      bm_status su = upload(tr);
+      if (su != BM_OK) return fail(su);
+      const int nt = static_cast<int>(tile_solve.size());
+      float ms = 0.f;
+      for (int rep = 0; rep < 2 && su == BM_OK; ++rep) {  // first run warms caches
+        BM_HIPB(hipEventRecord(t0, stream));
+        su = launch_batch_assign(P, d, C, deg_d, sv_d, tiles_d, nt, tr, kmax, sums_lds, sums, cnt,
+                                 tile_f, nullptr, 1, grid, stream);
+        BM_HIPB(hipEventRecord(t1, stream));
+        BM_HIPB(hipEventSynchronize(t1));
+        BM_HIPB(hipEventElapsedTime(&ms, t0, t1));
+      }
+      if (su != BM_OK) return fail(su);
+      if (tile_rows == 0 || ms < best) {
+        best = ms;
+        tile_rows = tr;
+      }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    g_tile_cache[shape] = tile_rows;
+  }
+  if ((st = upload(tile_rows)) != BM_OK) return fail(st);
+  const int nt = static_cast<int>(tile_solve.size());
+
+  // one round = assignment + update, captured once and launched per round
+  BM_HIPB(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  bm_status cs = launch_batch_assign(P, d, C, deg_d, sv_d, tiles_d, nt, tile_rows, kmax, sums_lds,
+                                     sums, cnt, tile_f, labels, 0, grid, stream);
+  if (cs == BM_OK)
+    cs = launch_batch_update(sv_d, n_solves, tile_f, sums, cnt, C, c64, deg_d, d, o.max_iter, o.tol,
+                             o.stop_rule, running, stream);
+  const hipError_t ce = hipStreamEndCapture(stream, &graph);
+  if (cs != BM_OK) return fail(cs);
+  if (ce != hipSuccess)
+    return fail(set_error(BM_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce)));
+  BM_HIPB(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  int still = 1;
+  int rounds = 0;
+  for (; rounds <= o.max_iter && still; ++rounds) {
+    BM_HIPB(hipMemsetAsync(running, 0, sizeof(int), stream));
+    BM_HIPB(hipGraphLaunch(exec, stream));
+    BM_HIPB(hipMemcpyAsync(&still, running, sizeof(int), hipMemcpyDeviceToHost, stream));
+    BM_HIPB(hipStreamSynchronize(stream));
+  }
+  if (still) return fail(set_error(BM_EDEVICE, "batched Lloyd did not finish in max_iter + 1 rounds"));
+  BM_HIPB(hipMemcpyAsync(hs.data(), sv_d, sizeof(BatchSolve) * n_solves, hipMemcpyDeviceToHost, stream));
+  BM_HIPB(hipMemcpyAsync(deg, deg_d, static_cast<size_t>(ktot), hipMemcpyDeviceToHost, stream));
+  BM_HIPB(hipEventRecord(ev_out, stream));
+  BM_HIPB(hipStreamWaitEvent(user, ev_out, 0));
+  BM_HIPB(hipStreamSynchronize(stream));
+#undef BM_HIPB
+  for (int j = 0; j < n_solves; ++j) {
+    if (hs[j].status != kSolveDone) return fail(set_error(BM_EDEVICE, "solve %d did not finish", j));
+    if (f) f[j] = hs[j].f;
+    if (passes) passes[j] = hs[j].passes;
+  }
+  g_last_batch_rounds = rounds;
+  g_last_batch_tile = tile_rows;
+  cleanup();
+  return BM_OK;
+}
+
+// Rounds and rows per tile of the last kmeans_lloyd_batched on this thread
+// (diagnostics; not declared in the public header).
+int32_t bm_debug_batch_info(int32_t* rounds, int32_t* tile_rows) {
+  if (rounds) *rounds = g_last_batch_rounds;
+  if (tile_rows) *tile_rows = g_last_batch_tile;
+  return BM_OK;
 }
 
 }  // extern "C"

@@ -128,6 +128,31 @@ bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float
                         hipStream_t stream);
 int assign_grid(int64_t n);
 
+// Batched Lloyd (bm_batch.hip): per-solve state, laid out in device memory.
+constexpr int kSolveRunning = 0;  // next round: assignment + update
+constexpr int kSolveFinal = 1;    // next round: the last assignment only
+constexpr int kSolveDone = 2;
+struct BatchSolve {
+  int64_t row0, s;      // rows of P
+  int32_t c0, k;        // rows of C
+  int32_t tile0, ntiles;
+  int32_t status, iter;  // iter: 1-based index of the next assignment
+  int32_t passes, pad;
+  double f, f_prev;
+};
+size_t batch_assign_lds(int d, int kmax, bool sums_lds);
+bm_status batch_assign_grid(int d, int kmax, bool sums_lds, int* grid);
+bm_status launch_batch_assign(const float* P, int d, const float* C, const uint8_t* deg,
+                              const BatchSolve* sv, const int32_t* tile_solve, int ntiles,
+                              int tile_rows, int kmax, bool sums_lds, double* sums, int32_t* cnt,
+                              double* tile_f, int32_t* labels, int dry, int grid, hipStream_t stream);
+bm_status launch_batch_update(BatchSolve* sv, int n_solves, const double* tile_f, double* sums,
+                              int32_t* cnt, float* C, double* C64, uint8_t* deg, int d, int max_iter,
+                              double tol, int stop_rule, int* running, hipStream_t stream);
+bm_status launch_batch_init(const float* C, double* C64, int64_t n, hipStream_t stream);
+bm_status launch_gather_rows(const void* X, int x_bf16, int64_t n, int d, const int32_t* idx,
+                             int64_t s, float* P, int* bad, hipStream_t stream);
+
 // BF16 matrix-core assignment (bm_assign_mfma.hip): plan checks the shape and
 // picks the grid; the launch writes the same outputs as launch_assign and
 // adds the number of points it recomputed on the FP32 path to *rechecked.

@@ -112,3 +112,28 @@ def test_product_philox_matches_oracle_on_host():
     for i in range(0, 1_000_000, 997):
         fold ^= oracle.sample_key(seed, t, i) ^ oracle.seed_word(seed, t, i)
     assert got[8] == fold
+
+
+def test_batched_and_gather_reject_invalid_arguments(bm):
+    lib = bm.load()
+    P = ct.c_void_p(16)
+    C = ct.c_void_p(16)
+
+    def batched(n_solves, s, k, deg, P=P, C=C):
+        s = np.ascontiguousarray(s, np.int64)
+        k = np.ascontiguousarray(k, np.int32)
+        return lib.kmeans_lloyd_batched(n_solves, P, 2, s.ctypes.data_as(ct.c_void_p),
+                                        k.ctypes.data_as(ct.c_void_p), C,
+                                        deg.ctypes.data_as(ct.c_void_p), None, None, None, None)
+
+    deg = np.zeros(9, np.uint8)
+    assert batched(2, [10, 5], [3, 6], deg) == bm.BM_EINVAL          # k > s
+    assert batched(0, [10], [3], deg) == bm.BM_EINVAL                # no solves
+    assert batched(2, [10, 0], [3, 1], deg) == bm.BM_EINVAL          # empty solve
+    assert batched(1, [10], [3], deg, P=None) == bm.BM_EINVAL        # no P
+    assert batched(1, [10], [3], np.ones(3, np.uint8)) == bm.BM_EINVAL  # all degenerate
+    idx = ct.c_void_p(16)
+    assert lib.bm_gather_rows(ct.c_void_p(16), 0, 2, idx, 5, P, None) == bm.BM_EINVAL
+    assert lib.bm_gather_rows(ct.c_void_p(16), 10, 2, None, 5, P, None) == bm.BM_EINVAL
+    assert lib.bm_gather_rows(ct.c_void_p(16), 10, 0, idx, 5, P, None) == bm.BM_EINVAL
+    assert lib.bm_last_error()
