@@ -785,6 +785,8 @@ bm_status kmeans_lloyd_batched(int32_t n_solves, const float* P, int32_t d, cons
   double* sums = nullptr;
   int32_t* cnt = nullptr;
   double* c64 = nullptr;
+  float* cpad = nullptr;
+  float* ppad = nullptr;
   uint8_t* deg_d = nullptr;
   int* running = nullptr;
   char* base = nullptr;
@@ -794,9 +796,11 @@ bm_status kmeans_lloyd_batched(int32_t n_solves, const float* P, int32_t d, cons
     sv_d = L.take<BatchSolve>(n_solves);
     tiles_d = L.take<int32_t>(max_tiles);
     tile_f = L.take<double>(max_tiles);
-    sums = L.take<double>(ktot * d);
+    sums = L.take<double>(ktot * padded_dim(d));
     cnt = L.take<int32_t>(ktot);
     c64 = L.take<double>(ktot * d);
+    cpad = L.take<float>(ktot * padded_dim(d));
+    ppad = L.take<float>(padded_dim(d) == d ? 1 : rows * padded_dim(d));
     deg_d = L.take<uint8_t>(ktot);
     running = L.take<int>(1);
     if (round == 0) {
@@ -833,9 +837,15 @@ bm_status kmeans_lloyd_batched(int32_t n_solves, const float* P, int32_t d, cons
   BM_HIPB(hipEventRecord(ev_in, user));
   BM_HIPB(hipStreamWaitEvent(stream, ev_in, 0));
   BM_HIPB(hipMemcpyAsync(deg_d, deg, static_cast<size_t>(ktot), hipMemcpyHostToDevice, stream));
-  BM_HIPB(hipMemsetAsync(sums, 0, sizeof(double) * ktot * d, stream));
+  BM_HIPB(hipMemsetAsync(sums, 0, sizeof(double) * ktot * padded_dim(d), stream));
   BM_HIPB(hipMemsetAsync(cnt, 0, sizeof(int32_t) * ktot, stream));
-  if ((st = launch_batch_init(C, c64, ktot * d, stream)) != BM_OK) return fail(st);
+  if ((st = launch_batch_init(C, c64, cpad, ktot, d, stream)) != BM_OK) return fail(st);
+  // rows DM wide for guard-free loads (a copy only when d is not already DM)
+  const float* Pp = P;
+  if (padded_dim(d) != d) {
+    if ((st = launch_pad_rows(P, ppad, rows, d, stream)) != BM_OK) return fail(st);
+    Pp = ppad;
+  }
 
   // rows per tile: tuned once per shape by timing a dry assignment pass
   std::vector<int32_t> tile_solve, tile0, ntiles;
@@ -869,8 +879,8 @@ bm_status kmeans_lloyd_batched(int32_t n_solves, const float* P, int32_t d, cons
       float ms = 0.f;
       for (int rep = 0; rep < 2 && su == BM_OK; ++rep) {  // first run warms caches
         BM_HIPB(hipEventRecord(t0, stream));
-        su = launch_batch_assign(P, d, C, deg_d, sv_d, tiles_d, nt, tr, kmax, sums_lds, sums, cnt,
-                                 tile_f, nullptr, 1, grid, stream);
+        su = launch_batch_assign(Pp, d, C, cpad, deg_d, sv_d, tiles_d, nt, tr, kmax, sums_lds, sums,
+                                 cnt, tile_f, nullptr, 1, grid, stream);
         BM_HIPB(hipEventRecord(t1, stream));
         BM_HIPB(hipEventSynchronize(t1));
         BM_HIPB(hipEventElapsedTime(&ms, t0, t1));
@@ -890,11 +900,11 @@ bm_status kmeans_lloyd_batched(int32_t n_solves, const float* P, int32_t d, cons
 
   // one round = assignment + update, captured once and launched per round
   BM_HIPB(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-  bm_status cs = launch_batch_assign(P, d, C, deg_d, sv_d, tiles_d, nt, tile_rows, kmax, sums_lds,
-                                     sums, cnt, tile_f, labels, 0, grid, stream);
+  bm_status cs = launch_batch_assign(Pp, d, C, cpad, deg_d, sv_d, tiles_d, nt, tile_rows, kmax,
+                                     sums_lds, sums, cnt, tile_f, labels, 0, grid, stream);
   if (cs == BM_OK)
-    cs = launch_batch_update(sv_d, n_solves, tile_f, sums, cnt, C, c64, deg_d, d, o.max_iter, o.tol,
-                             o.stop_rule, running, stream);
+    cs = launch_batch_update(sv_d, n_solves, tile_f, sums, cnt, C, cpad, c64, deg_d, d, o.max_iter,
+                             o.tol, o.stop_rule, running, stream);
   const hipError_t ce = hipStreamEndCapture(stream, &graph);
   if (cs != BM_OK) return fail(cs);
   if (ce != hipSuccess)

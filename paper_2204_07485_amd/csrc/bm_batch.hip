@@ -29,12 +29,17 @@ namespace {
 
 constexpr int kBatchBlock = 256;
 
-__device__ __forceinline__ int batch_sums_ld(int d) { return (d & 1) ? d : d + 1; }
+// Cluster sums are kept DM wide (the zero padding of the rows adds exact
+// zeros), so the unrolled accumulation needs no per-column guard; in LDS the
+// row stride is DM + 1 (odd, spreading rows over the banks).
+template <int DM>
+__device__ __forceinline__ constexpr int batch_sums_ld() { return DM + 1; }
 
 template <int DM, bool SUMS_LDS>
 __global__ void __launch_bounds__(kBatchBlock)
-    batch_assign_kernel(const float* __restrict__ P, int d, const float* __restrict__ C,
-                        const uint8_t* __restrict__ deg, const BatchSolve* __restrict__ sv,
+    batch_assign_kernel(const float* __restrict__ Pp, int d, const float* __restrict__ C,
+                        const float* __restrict__ Cpad, const uint8_t* __restrict__ deg,
+                        const BatchSolve* __restrict__ sv,
                         const int32_t* __restrict__ tile_solve, int ntiles, int tile_rows,
                         double* __restrict__ sums, int32_t* __restrict__ cnt,
                         double* __restrict__ tile_f, int32_t* __restrict__ labels, int dry) {
@@ -69,7 +74,7 @@ __global__ void __launch_bounds__(kBatchBlock)
     int* cnt_l = act + k;
     double* sums_l = reinterpret_cast<double*>(
         lds_raw + ((sizeof(float) * static_cast<size_t>(k) * DM + sizeof(int) * 2 * k + 15) & ~size_t(15)));
-    const int ld = batch_sums_ld(d);
+    constexpr int ld = batch_sums_ld<DM>();
     for (int e = tid; e < k * DM; e += kBatchBlock) {
       const int j = e / DM;
       const int tdim = e - j * DM;
@@ -96,25 +101,38 @@ __global__ void __launch_bounds__(kBatchBlock)
     double f = 0.0;
     for (int64_t i = r0 + tid; i < r1; i += kBatchBlock) {
       float x[DM];
-      load_row_f32<DM>(P + static_cast<size_t>(i) * d, d, x);
+      {  // rows are DM wide and zero padded: 16-byte loads, no column guard
+        const float4* r4 = reinterpret_cast<const float4*>(Pp + static_cast<size_t>(i) * DM);
+#pragma unroll
+        for (int q = 0; q < DM / 4; ++q) {
+          const float4 v = r4[q];
+          x[4 * q + 0] = v.x;
+          x[4 * q + 1] = v.y;
+          x[4 * q + 2] = v.z;
+          x[4 * q + 3] = v.w;
+        }
+      }
       int bj;
       float bd;
-      nearest_f32<DM>(x, Cl, act, na, bj, bd);
-      f += dist2_f64_row<DM>(x, Cl + bj * DM);
+      nearest_f32_sgpr<DM>(x, Cpad + static_cast<size_t>(c0) * DM, act, na, bj, bd);
       if (labels && !dry) labels[i] = bj;
+      const float* cw = Cl + bj * DM;
       if (accumulate) {
+        // FP64 distance of the winner (dimension order, as dist2_f64_row) fused
+        // with the accumulation, so each widened coordinate is used at once
         atomicAdd(&cnt_l[bj], 1);
-        if (SUMS_LDS) {
-          double* dst = sums_l + bj * ld;
+        double* dst = SUMS_LDS ? sums_l + bj * ld : sums + static_cast<size_t>(c0 + bj) * DM;
+        double acc = 0.0;
 #pragma unroll
-          for (int tdim = 0; tdim < DM; ++tdim)
-            if (tdim < d) unsafeAtomicAdd(dst + tdim, static_cast<double>(x[tdim]));
-        } else {
-          double* dst = sums + static_cast<size_t>(c0 + bj) * d;
-#pragma unroll
-          for (int tdim = 0; tdim < DM; ++tdim)
-            if (tdim < d) unsafeAtomicAdd(dst + tdim, static_cast<double>(x[tdim]));
+        for (int tdim = 0; tdim < DM; ++tdim) {
+          const double xv = static_cast<double>(x[tdim]);
+          const double e = xv - static_cast<double>(cw[tdim]);
+          acc = __builtin_fma(e, e, acc);
+          unsafeAtomicAdd(dst + tdim, xv);
         }
+        f += acc;
+      } else {
+        f += dist2_f64_row<DM>(x, cw);
       }
     }
     const double ft = block_sum_f64<kBatchBlock>(f, s_tmp);
@@ -124,7 +142,9 @@ __global__ void __launch_bounds__(kBatchBlock)
       if (SUMS_LDS) {
         for (int e = tid; e < k * d; e += kBatchBlock) {
           const int j = e / d;
-          if (cnt_l[j]) unsafeAtomicAdd(&sums[static_cast<size_t>(c0) * d + e], sums_l[j * ld + (e - j * d)]);
+          const int tdim = e - j * d;
+          if (cnt_l[j])
+            unsafeAtomicAdd(&sums[static_cast<size_t>(c0 + j) * DM + tdim], sums_l[j * ld + tdim]);
         }
       }
       for (int j = tid; j < k; j += kBatchBlock)
@@ -139,8 +159,9 @@ __global__ void __launch_bounds__(kBatchBlock)
 __global__ void __launch_bounds__(kBatchBlock)
     batch_update_kernel(BatchSolve* __restrict__ sv, const double* __restrict__ tile_f,
                         double* __restrict__ sums, int32_t* __restrict__ cnt, float* __restrict__ C,
-                        double* __restrict__ C64, uint8_t* __restrict__ deg, int d, int max_iter,
-                        double tol, int stop_rule, int* __restrict__ running) {
+                        float* __restrict__ Cpad, int dm, double* __restrict__ C64,
+                        uint8_t* __restrict__ deg, int d, int max_iter, double tol, int stop_rule,
+                        int* __restrict__ running) {
   __shared__ double s_tmp[kBatchBlock / kWave + 1];
   __shared__ double s_max[kBatchBlock / kWave];
   __shared__ int s_done;
@@ -172,7 +193,7 @@ __global__ void __launch_bounds__(kBatchBlock)
   if (s_done) {
     // the last assignment of a solve stopped by the objective rule filled its
     // sums; leave them cleared like every other round
-    for (int e = tid; e < k * d; e += kBatchBlock) sums[static_cast<size_t>(c0) * d + e] = 0.0;
+    for (int e = tid; e < k * dm; e += kBatchBlock) sums[static_cast<size_t>(c0) * dm + e] = 0.0;
     for (int j = tid; j < k; j += kBatchBlock) cnt[c0 + j] = 0;
     return;
   }
@@ -184,7 +205,7 @@ __global__ void __launch_bounds__(kBatchBlock)
     const int c = cnt[row];
     float* cj = C + row * d;
     double* cj64 = C64 + row * d;
-    double* sj = sums + row * d;
+    double* sj = sums + row * dm;
     if (c == 0) {
       deg[row] = 1;
       for (int tdim = 0; tdim < d; ++tdim) cj[tdim] = __builtin_nanf("");
@@ -197,8 +218,9 @@ __global__ void __launch_bounds__(kBatchBlock)
       moved = __dadd_rn(moved, __dmul_rn(diff, diff));
       cj64[tdim] = mean;
       cj[tdim] = static_cast<float>(mean);
-      sj[tdim] = 0.0;
+      Cpad[row * dm + tdim] = static_cast<float>(mean);
     }
+    for (int tdim = 0; tdim < dm; ++tdim) sj[tdim] = 0.0;
     cnt[row] = 0;
     moved = sqrt(moved);
     local = moved > local ? moved : local;
@@ -225,11 +247,31 @@ __global__ void __launch_bounds__(kBatchBlock)
   }
 }
 
-// Seed the FP64 means from the FP32 start centroids.
-__global__ void batch_init_kernel(const float* __restrict__ C, double* __restrict__ C64, int64_t n) {
+// Seed the FP64 means and the zero-padded FP32 copy from the start centroids
+// (rows x d).
+__global__ void batch_init_kernel(const float* __restrict__ C, double* __restrict__ C64,
+                                  float* __restrict__ Cpad, int64_t rows, int d, int dm) {
+  const int64_t n = rows * dm;
   for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    C64[e] = static_cast<double>(C[e]);
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = e / dm;
+    const int t = static_cast<int>(e - r * dm);
+    const float v = t < d ? C[r * d + t] : 0.f;
+    Cpad[e] = v;
+    if (t < d) C64[r * d + t] = static_cast<double>(v);
+  }
+}
+
+// Copy rows (d wide) into rows DM wide, zero padded.
+__global__ void pad_rows_kernel(const float* __restrict__ P, float* __restrict__ Pp, int64_t rows,
+                                int d, int dm) {
+  const int64_t n = rows * dm;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = e / dm;
+    const int t = static_cast<int>(e - r * dm);
+    Pp[e] = t < d ? P[r * d + t] : 0.f;
+  }
 }
 
 // Gather rows of X (FP32 or BF16 widened exactly) into P: one wavefront per row.
@@ -282,7 +324,7 @@ const void* pick_batch_assign(int dm) {
 size_t batch_assign_lds(int d, int kmax, bool sums_lds) {
   const int dm = padded_dim(d);
   size_t b = (sizeof(float) * static_cast<size_t>(kmax) * dm + sizeof(int) * 2 * kmax + 15) & ~size_t(15);
-  if (sums_lds) b += sizeof(double) * static_cast<size_t>(kmax) * ((d & 1) ? d : d + 1);
+  if (sums_lds) b += sizeof(double) * static_cast<size_t>(kmax) * (dm + 1);
   return b;
 }
 
@@ -303,15 +345,16 @@ bm_status batch_assign_grid(int d, int kmax, bool sums_lds, int* grid) {
   return BM_OK;
 }
 
-bm_status launch_batch_assign(const float* P, int d, const float* C, const uint8_t* deg,
-                              const BatchSolve* sv, const int32_t* tile_solve, int ntiles,
-                              int tile_rows, int kmax, bool sums_lds, double* sums, int32_t* cnt,
-                              double* tile_f, int32_t* labels, int dry, int grid, hipStream_t stream) {
+bm_status launch_batch_assign(const float* Pp, int d, const float* C, const float* Cpad,
+                              const uint8_t* deg, const BatchSolve* sv, const int32_t* tile_solve,
+                              int ntiles, int tile_rows, int kmax, bool sums_lds, double* sums,
+                              int32_t* cnt, double* tile_f, int32_t* labels, int dry, int grid,
+                              hipStream_t stream) {
   const void* fn = sums_lds ? pick_batch_assign<true>(padded_dim(d)) : pick_batch_assign<false>(padded_dim(d));
   if (!fn || grid < 1) return set_error(BM_EINVAL, "batched assignment: bad plan");
   const size_t lds = batch_assign_lds(d, kmax, sums_lds);
-  void* args[] = {const_cast<float**>(&P), &d, const_cast<float**>(&C), const_cast<uint8_t**>(&deg),
-                  const_cast<BatchSolve**>(&sv), const_cast<int32_t**>(&tile_solve), &ntiles,
+  void* args[] = {const_cast<float**>(&Pp), &d, const_cast<float**>(&C), const_cast<float**>(&Cpad),
+                  const_cast<uint8_t**>(&deg), const_cast<BatchSolve**>(&sv), const_cast<int32_t**>(&tile_solve), &ntiles,
                   &tile_rows, &sums, &cnt, &tile_f, &labels, &dry};
   const hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kBatchBlock), args, lds, stream);
   if (e != hipSuccess)
@@ -320,22 +363,39 @@ bm_status launch_batch_assign(const float* P, int d, const float* C, const uint8
 }
 
 bm_status launch_batch_update(BatchSolve* sv, int n_solves, const double* tile_f, double* sums,
-                              int32_t* cnt, float* C, double* C64, uint8_t* deg, int d, int max_iter,
-                              double tol, int stop_rule, int* running, hipStream_t stream) {
+                              int32_t* cnt, float* C, float* Cpad, double* C64, uint8_t* deg, int d,
+                              int max_iter, double tol, int stop_rule, int* running,
+                              hipStream_t stream) {
+  const int dm = padded_dim(d);
   hipLaunchKernelGGL(batch_update_kernel, dim3(n_solves), dim3(kBatchBlock), 0, stream, sv, tile_f,
-                     sums, cnt, C, C64, deg, d, max_iter, tol, stop_rule, running);
+                     sums, cnt, C, Cpad, dm, C64, deg, d, max_iter, tol, stop_rule, running);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess)
     return set_error(BM_EDEVICE, "batched update launch failed: %s", hipGetErrorString(e));
   return BM_OK;
 }
 
-bm_status launch_batch_init(const float* C, double* C64, int64_t n, hipStream_t stream) {
-  const int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(batch_init_kernel, dim3(static_cast<unsigned>(blocks < 1024 ? (blocks < 1 ? 1 : blocks) : 1024)),
-                     dim3(256), 0, stream, C, C64, n);
+bm_status launch_batch_init(const float* C, double* C64, float* Cpad, int64_t rows, int d,
+                            hipStream_t stream) {
+  const int dm = padded_dim(d);
+  const int64_t blocks = (rows * dm + 255) / 256;
+  hipLaunchKernelGGL(batch_init_kernel,
+                     dim3(static_cast<unsigned>(blocks < 1024 ? (blocks < 1 ? 1 : blocks) : 1024)),
+                     dim3(256), 0, stream, C, C64, Cpad, rows, d, dm);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(BM_EDEVICE, "batch init launch failed: %s", hipGetErrorString(e));
+  return BM_OK;
+}
+
+bm_status launch_pad_rows(const float* P, float* Pp, int64_t rows, int d, hipStream_t stream) {
+  const int dm = padded_dim(d);
+  int64_t blocks = (rows * dm + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(pad_rows_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, P, Pp,
+                     rows, d, dm);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(BM_EDEVICE, "pad launch failed: %s", hipGetErrorString(e));
   return BM_OK;
 }
 

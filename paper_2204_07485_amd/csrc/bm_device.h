@@ -248,6 +248,40 @@ __device__ __forceinline__ void nearest_f32(const float (&x)[DM], const float* _
   }
 }
 
+// The same nearest-centroid search with the centroid rows read through the
+// scalar data cache into SGPRs: every lane compares its row with the same
+// centroid, so the values are wavefront-uniform and the inner loop is two
+// VALU operations per coordinate with an SGPR operand, no LDS traffic.
+// Cpad holds the centroids zero-padded to DM columns (read only during the
+// kernel); `act` (LDS) lists the na active slots ascending.  Identical
+// arithmetic to nearest_f32.
+typedef const float __attribute__((address_space(4))) scalar_f32;
+
+template <int DM>
+__device__ __forceinline__ void nearest_f32_sgpr(const float (&x)[DM], const float* __restrict__ Cpad,
+                                                 const int* __restrict__ act, int na, int& best_j,
+                                                 float& best_d) {
+  best_j = -1;
+  best_d = __builtin_inff();
+  for (int a = 0; a < na; ++a) {
+    const int j = __builtin_amdgcn_readfirstlane(act[a]);
+    const scalar_f32* c = (const scalar_f32*)(Cpad) + static_cast<size_t>(j) * DM;
+    float acc = 0.f;
+#pragma unroll
+    for (int t = 0; t < DM; ++t) {
+      const float e = x[t] - c[t];
+      acc = __builtin_fmaf(e, e, acc);
+      // keep the scalar loads of one 16-column chunk from being hoisted
+      // above the previous chunk (bounded SGPR use)
+      if ((t & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (acc < best_d) {
+      best_d = acc;
+      best_j = j;
+    }
+  }
+}
+
 // Squared distance in FP64 of a register row to a padded LDS row (the
 // objective of the chosen centroid; padding contributes exact zeros).
 template <int DM>

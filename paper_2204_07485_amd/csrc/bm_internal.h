@@ -142,14 +142,19 @@ struct BatchSolve {
 };
 size_t batch_assign_lds(int d, int kmax, bool sums_lds);
 bm_status batch_assign_grid(int d, int kmax, bool sums_lds, int* grid);
-bm_status launch_batch_assign(const float* P, int d, const float* C, const uint8_t* deg,
-                              const BatchSolve* sv, const int32_t* tile_solve, int ntiles,
-                              int tile_rows, int kmax, bool sums_lds, double* sums, int32_t* cnt,
-                              double* tile_f, int32_t* labels, int dry, int grid, hipStream_t stream);
+// Pp: rows DM = padded_dim(d) wide, zero padded (launch_pad_rows).
+bm_status launch_batch_assign(const float* Pp, int d, const float* C, const float* Cpad,
+                              const uint8_t* deg, const BatchSolve* sv, const int32_t* tile_solve,
+                              int ntiles, int tile_rows, int kmax, bool sums_lds, double* sums,
+                              int32_t* cnt, double* tile_f, int32_t* labels, int dry, int grid,
+                              hipStream_t stream);
 bm_status launch_batch_update(BatchSolve* sv, int n_solves, const double* tile_f, double* sums,
-                              int32_t* cnt, float* C, double* C64, uint8_t* deg, int d, int max_iter,
-                              double tol, int stop_rule, int* running, hipStream_t stream);
-bm_status launch_batch_init(const float* C, double* C64, int64_t n, hipStream_t stream);
+                              int32_t* cnt, float* C, float* Cpad, double* C64, uint8_t* deg, int d,
+                              int max_iter, double tol, int stop_rule, int* running,
+                              hipStream_t stream);
+bm_status launch_batch_init(const float* C, double* C64, float* Cpad, int64_t rows, int d,
+                            hipStream_t stream);
+bm_status launch_pad_rows(const float* P, float* Pp, int64_t rows, int d, hipStream_t stream);
 bm_status launch_gather_rows(const void* X, int x_bf16, int64_t n, int d, const int32_t* idx,
                              int64_t s, float* P, int* bad, hipStream_t stream);
 
