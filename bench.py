@@ -22,6 +22,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 direct differences take two VALU instructions (subtract, FMA) per
+# coordinate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 FLOP / 2 instructions
+FP32_DD_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 2 / 1e12
 COUNTERS = os.path.join(ROOT, "profiles", "solver_medium_hbm_counters.md")
 
 
@@ -65,6 +68,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=12,
                     help="samples the CPU oracle runs for its bounded baseline")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-solves workload")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the BF16 workload's mixed-precision (MFMA) comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -145,6 +150,114 @@ def mixed_precision(reps=5):
                      "mfma_tflops": 2 * 2 * n * kp * d / (ms["bf16_mfma"] * 1e-3) / 1e12,
                      "fp32_path_tflops": 2 * n * k * d / (ms["fp32"] * 1e-3) / 1e12},
     }
+
+
+def batched_solves(n_seq=16):
+    """The batched workload: 10,000,000 x 68 FP32 (50 components, diagonal
+    variances U[0.2, 3], Dirichlet weights, seed 3); 256 solves with
+    s ~ U{5,000..100,000} and k cycling through (5, 10, 25, 50), each started
+    like a Big-means run's first sample (its sample, rows and K-means++
+    centres); then K-means on all of them at once, one graph launch per round,
+    against the first n_seq solves run one after another."""
+    import numpy as np
+    import torch
+
+    from paper_2204_07485_amd import bigmeans, synth
+    X = torch.from_numpy(synth.make_wide()).to("cuda:0")
+    solves = synth.wide_solves()
+    P, s, k, C, deg = bigmeans.prepare_batch(X, solves)
+    del X
+    kw = dict(max_iter=300, tol=1e-4, stop_rule=bigmeans.BM_STOP_REL_OBJ)
+    bigmeans.kmeans_lloyd_batched(P, s, k, C.clone(), deg, want_labels=False, **kw)  # tunes tiles
+    Cr = C.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dg, _, f, passes, info = bigmeans.kmeans_lloyd_batched(P, s, k, Cr, deg, want_labels=False, **kw)
+    wall = (time.perf_counter() - t0) * 1e3
+    d = P.shape[1]
+    rows_passes = float((passes.astype(np.float64) * s).sum())
+    dev_ms = float(sum(info["round_ms"]))
+    r0 = np.concatenate([[0], np.cumsum(s)])
+    c0 = np.concatenate([[0], np.cumsum(k)])
+    t1 = time.perf_counter()
+    seq_rows = 0.0
+    for j in range(n_seq):
+        Cj = C[c0[j]:c0[j + 1]].clone()
+        _, _, _, sp = bigmeans.kmeans_lloyd(P[r0[j]:r0[j + 1]], Cj, deg[c0[j]:c0[j + 1]], **kw)
+        seq_rows += sp * s[j]
+    seq_ms = (time.perf_counter() - t1) * 1e3
+    # first round: every solve active, the full sample set streamed once
+    first_bytes = float(s.sum()) * 72 * 4  # rows are read padded to 72 columns
+    first_ms = info["round_ms"][0]
+    gbs = first_bytes / (first_ms * 1e-3) / 1e9
+    return {
+        "workload": "batched: 10,000,000 x 68 FP32 (50 components), 256 solves, s ~ U{5k..100k}, "
+                    "k in (5,10,25,50), relative-objective stop 1e-4 / 300 rounds",
+        "rows": int(s.sum()), "rounds": info["rounds"], "tile_rows": info["tile_rows"],
+        "ms_wall": wall, "ms_device_rounds": dev_ms,
+        "rows_x_passes_per_s": rows_passes / (wall * 1e-3),
+        "sequential_rows_x_passes_per_s": seq_rows / (seq_ms * 1e-3),
+        "speedup_vs_sequential": (rows_passes / wall) / (seq_rows / seq_ms),
+        "roofline_first_round": {"bound": "alu", "kernel": "batch_assign_kernel<72,true>",
+                                 "achieved_gbs": gbs, "peak_gbs": HBM_PEAK_GBS,
+                                 "hbm_frac": gbs / HBM_PEAK_GBS, "ms": first_ms,
+                                 "tflops": float((s * k).sum()) * 68 * 2 / (first_ms * 1e-3) / 1e12,
+                                 "fp32_direct_difference_peak_tflops": FP32_DD_PEAK_TFLOPS},
+    }
+
+
+def serve_stream(n_jobs=200, slots=4, rate=200.0, seed=5):
+    """The serving workload: Poisson arrivals (rate jobs/s) of jobs with
+    n = floor(exp(U[ln 1e4, ln 1e6])), d from {2, 8, 16, 32, 68, 128}, k from
+    U{2..50}, s = min(n, 50,000), 20 samples; each job's data is a k-component
+    Gaussian mixture (means U[-10, 10]^d, sigma U[0.5, 2]) generated on the
+    GPU from the job's seed before timing.  Jobs are submitted at their
+    arrival times; latency = completion - arrival."""
+    import numpy as np
+    import torch
+
+    from paper_2204_07485_amd import bigmeans, synth
+    jobs = synth.serve_jobs(n_jobs, rate=rate, seed=seed)
+    data = []
+    for j in jobs:
+        g = torch.Generator(device="cuda:0").manual_seed(j["seed"] % (2**63))
+        means = torch.rand((j["k"], j["d"]), generator=g, device="cuda:0") * 20 - 10
+        sig = torch.rand((j["k"], 1), generator=g, device="cuda:0") * 1.5 + 0.5
+        comp = torch.randint(0, j["k"], (j["n"],), generator=g, device="cuda:0")
+        X = means[comp] + sig[comp] * torch.randn((j["n"], j["d"]), generator=g, device="cuda:0")
+        data.append(X.contiguous())
+    torch.cuda.synchronize()
+    kw = dict(max_iter=300, tol=1e-4, stop_rule=bigmeans.BM_STOP_REL_OBJ, n_local_trials=3)
+    out = {}
+    for nslots in sorted({1, 2, slots}):
+        with bigmeans.Server(slots=nslots) as srv:
+            for j, X in list(zip(jobs, data))[:4]:  # warm-up
+                srv.result(srv.submit(X, j["k"], j["s"], j["n_samples"], j["seed"], **kw))
+            t_ref = None
+            ids = []
+            t0 = time.perf_counter()
+            for j, X in zip(jobs, data):
+                delay = t0 + j["arrival"] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                ids.append(srv.submit(X, j["k"], j["s"], j["n_samples"], j["seed"], **kw))
+            res = [srv.result(i) for i in ids]
+            info = srv.info()
+        sub = np.array([r["t_submit_ms"] for r in res])
+        end = np.array([r["t_end_ms"] for r in res])
+        lat = end - sub
+        span_s = (end.max() - sub.min()) / 1e3
+        out[f"slots_{nslots}"] = {
+            "jobs": len(res), "jobs_per_s": len(res) / span_s,
+            "latency_ms_p50": float(np.percentile(lat, 50)),
+            "latency_ms_p99": float(np.percentile(lat, 99)),
+            "service_ms_mean": float(np.mean(end - np.array([r["t_start_ms"] for r in res]))),
+            "peak_scratch_mb": info["peak_reserved_bytes"] / 1e6, "grid_per_job": info["grid_per_job"],
+            "failed": info["failed"]}
+    out["workload"] = (f"serving: {n_jobs} jobs, Poisson arrivals at {rate:g}/s, n log-uniform in "
+                       "[1e4, 1e6], d in {2,8,16,32,68,128}, k in [2,50], s = min(n, 50,000), "
+                       "20 samples, seed 5")
+    return out
 
 
 def main():
@@ -255,6 +368,12 @@ def main():
     if not args.no_mixed:
         print("mixed precision: BF16 workload ...", file=sys.stderr, flush=True)
         line["mixed_precision"] = mixed_precision()
+    if not args.no_batch:
+        print("batched solves ...", file=sys.stderr, flush=True)
+        line["batched"] = batched_solves()
+    if not args.no_serve:
+        print("serving stream ...", file=sys.stderr, flush=True)
+        line["serving"] = serve_stream()
     if not args.no_cpu_baseline:
         print("cpu baseline (oracle, 1 thread) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(X, W, args.cpu_samples)

@@ -50,7 +50,8 @@ enum {
   BM_ENOMEM = -2,      /* device or host allocation failed                 */
   BM_EDEVICE = -3,     /* a HIP call or a kernel failed                    */
   BM_ENOTSUP = -4,     /* a valid request this build cannot serve          */
-  BM_ECANCELLED = -5   /* the work was cancelled                           */
+  BM_ECANCELLED = -5,  /* the work was cancelled                           */
+  BM_ETIMEDOUT = -6    /* a wait ran out of time (the work goes on)        */
 };
 
 enum { BM_F32 = 0, BM_BF16 = 1 };               /* element type of X       */
@@ -247,6 +248,87 @@ bm_status bm_gather_rows(const void* X, int64_t n, int32_t d, const int32_t* idx
 bm_status kmeans_lloyd_batched(int32_t n_solves, const float* P, int32_t d, const int64_t* s,
                                const int32_t* k, float* C, uint8_t* deg, const bm_options* opt,
                                int32_t* labels, double* f, int32_t* passes);
+
+/* ------------------------------------------------------------------------
+ * Serving: a context runs many bigmeans_fit jobs concurrently on one GPU.
+ *
+ * A context has `slots` workers, each with its own HIP stream and device
+ * scratch; jobs start strictly in submission order, each as soon as a slot is
+ * idle and the scratch it needs fits in hbm_budget together with what the
+ * other slots hold (X and the outputs are the caller's and are not counted).
+ * A job's cooperative grid is capped (CUs / slots by default) so that the
+ * solver kernels of all slots are co-resident.  A job gives the result
+ * bigmeans_fit gives for it alone (integer outputs identical; objectives and
+ * centroids equal to rounding).  Every entry point is thread safe.
+ */
+typedef struct bm_ctx bm_ctx;
+
+enum { BM_JOB_QUEUED = 0, BM_JOB_RUNNING = 1, BM_JOB_DONE = 2, BM_JOB_FAILED = 3,
+       BM_JOB_CANCELLED = 4 };
+
+typedef struct bm_serve_config {
+  uint32_t struct_size;   /* sizeof(bm_serve_config)                              */
+  int32_t slots;          /* concurrent jobs, 1..64 (default 4)                   */
+  int64_t hbm_budget;     /* device scratch the context may hold, bytes (8 GiB)   */
+  int32_t device;         /* HIP device; -1 = the caller's current device         */
+  int32_t grid_per_job;   /* cap of a job's cooperative grid; 0 = CUs / slots     */
+} bm_serve_config;
+
+/* One job: the arguments of bigmeans_fit.  opt.stream is ignored (the slot's
+ * stream is used); every pointer must stay valid until the job is finished. */
+typedef struct bm_job {
+  uint32_t struct_size;   /* sizeof(bm_job)                                       */
+  const void* X;          /* device n x d (FP32, or BF16 per opt.x_dtype)         */
+  int64_t n;
+  int32_t d, k;
+  int64_t s;
+  int32_t n_samples;
+  uint64_t seed;
+  bm_options opt;         /* filled by bm_default_options, then adjusted          */
+  float* centroids;       /* device k x d out                                     */
+  int32_t* labels;        /* device n out, or NULL                                */
+  uint8_t* degenerate;    /* host k out, or NULL                                  */
+  double* sse;            /* host out, or NULL (with labels NULL: no final pass)  */
+  bm_stats* stats;        /* host out, or NULL                                    */
+} bm_job;
+
+typedef struct bm_job_info {
+  uint32_t struct_size;   /* sizeof(bm_job_info)                                  */
+  int32_t state;          /* BM_JOB_*                                             */
+  bm_status result;       /* the job's status once finished                       */
+  int32_t slot;           /* slot it ran on, -1 before it starts                  */
+  int64_t footprint;      /* device scratch it needs, bytes                       */
+  double t_submit_ms, t_start_ms, t_end_ms;  /* steady clock, from bm_ctx_create  */
+  char error[160];        /* bm_last_error of a failed job                        */
+} bm_job_info;
+
+typedef struct bm_serve_info {
+  uint32_t struct_size;   /* sizeof(bm_serve_info)                                */
+  int32_t slots, grid_per_job;
+  int64_t submitted, completed, failed, cancelled, queued, running;
+  int64_t reserved_bytes, peak_reserved_bytes;  /* scratch held by the slots      */
+} bm_serve_info;
+
+/* Defaults for *cfg (struct_size set). */
+bm_status bm_serve_default_config(bm_serve_config* cfg);
+/* Create a context (cfg NULL = defaults); its worker threads start at once. */
+bm_status bm_ctx_create(const bm_serve_config* cfg, bm_ctx** ctx);
+/* Queue a job (validated as bigmeans_fit validates it; BM_ENOMEM when it needs
+ * more scratch than the whole budget).  Returns at once with its id. */
+bm_status bm_ctx_submit(bm_ctx* ctx, const bm_job* job, int64_t* job_id);
+/* State of a job (info->struct_size must be set). */
+bm_status bm_ctx_poll(bm_ctx* ctx, int64_t job_id, bm_job_info* info);
+/* Block until the job has finished (timeout_ms < 0: no limit); BM_ETIMEDOUT
+ * if it has not finished in time.  info may be NULL. */
+bm_status bm_ctx_wait(bm_ctx* ctx, int64_t job_id, int32_t timeout_ms, bm_job_info* info);
+/* Cancel a queued job (BM_EINVAL once it has started). */
+bm_status bm_ctx_cancel(bm_ctx* ctx, int64_t job_id);
+/* Forget a finished job's record. */
+bm_status bm_ctx_release(bm_ctx* ctx, int64_t job_id);
+/* Counters of the context. */
+bm_status bm_ctx_info(bm_ctx* ctx, bm_serve_info* info);
+/* Cancel queued jobs, wait for running ones, free everything.  NULL is a no-op. */
+bm_status bm_ctx_destroy(bm_ctx* ctx);
 
 #ifdef __cplusplus
 }

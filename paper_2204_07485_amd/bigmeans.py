@@ -15,6 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbigmeans.so")
 
 BM_OK, BM_EINVAL, BM_ENOMEM, BM_EDEVICE, BM_ENOTSUP, BM_ECANCELLED = 0, -1, -2, -3, -4, -5
+BM_ETIMEDOUT = -6
+BM_JOB_QUEUED, BM_JOB_RUNNING, BM_JOB_DONE, BM_JOB_FAILED, BM_JOB_CANCELLED = 0, 1, 2, 3, 4
 BM_F32, BM_BF16 = 0, 1
 BM_STOP_SHIFT, BM_STOP_REL_OBJ = 0, 1
 BM_CMP_FOPT, BM_CMP_RESAMPLE = 0, 1
@@ -22,7 +24,9 @@ BM_PREC_FP32, BM_PREC_BF16_MFMA = 0, 1
 
 FUNCTIONS = ["bm_default_options", "bm_last_error", "bm_release_scratch", "bm_abi_version",
              "bigmeans_fit", "kmeans_assign", "kmeanspp_seed", "kmeans_lloyd",
-             "bm_sample_indices", "bm_gather_rows", "kmeans_lloyd_batched"]
+             "bm_sample_indices", "bm_gather_rows", "kmeans_lloyd_batched",
+             "bm_serve_default_config", "bm_ctx_create", "bm_ctx_submit", "bm_ctx_poll",
+             "bm_ctx_wait", "bm_ctx_cancel", "bm_ctx_release", "bm_ctx_info", "bm_ctx_destroy"]
 
 
 class BigmeansError(RuntimeError):
@@ -52,6 +56,35 @@ class Stats(ct.Structure):
                 ("ms_lloyd", ct.c_double), ("ms_lloyd_pass", ct.c_double),
                 ("ms_lloyd_post", ct.c_double), ("ms_lloyd_wait", ct.c_double),
                 ("rechecked", ct.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}
+
+
+class ServeConfig(ct.Structure):
+    _fields_ = [("struct_size", ct.c_uint32), ("slots", ct.c_int32), ("hbm_budget", ct.c_int64),
+                ("device", ct.c_int32), ("grid_per_job", ct.c_int32)]
+
+
+class Job(ct.Structure):
+    _fields_ = [("struct_size", ct.c_uint32), ("X", ct.c_void_p), ("n", ct.c_int64),
+                ("d", ct.c_int32), ("k", ct.c_int32), ("s", ct.c_int64), ("n_samples", ct.c_int32),
+                ("seed", ct.c_uint64), ("opt", Options), ("centroids", ct.c_void_p),
+                ("labels", ct.c_void_p), ("degenerate", ct.c_void_p), ("sse", ct.c_void_p),
+                ("stats", ct.c_void_p)]
+
+
+class JobInfo(ct.Structure):
+    _fields_ = [("struct_size", ct.c_uint32), ("state", ct.c_int32), ("result", ct.c_int32),
+                ("slot", ct.c_int32), ("footprint", ct.c_int64), ("t_submit_ms", ct.c_double),
+                ("t_start_ms", ct.c_double), ("t_end_ms", ct.c_double), ("error", ct.c_char * 160)]
+
+
+class ServeInfo(ct.Structure):
+    _fields_ = [("struct_size", ct.c_uint32), ("slots", ct.c_int32), ("grid_per_job", ct.c_int32),
+                ("submitted", ct.c_int64), ("completed", ct.c_int64), ("failed", ct.c_int64),
+                ("cancelled", ct.c_int64), ("queued", ct.c_int64), ("running", ct.c_int64),
+                ("reserved_bytes", ct.c_int64), ("peak_reserved_bytes", ct.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}
@@ -88,12 +121,32 @@ def load(path=LIB_PATH):
     L.kmeans_lloyd.restype = I32
     L.bm_sample_indices.argtypes = [I64, I64, U64, I32, P, P]
     L.bm_sample_indices.restype = I32
+    L.bm_serve_default_config.argtypes = [P]
+    L.bm_serve_default_config.restype = I32
+    L.bm_ctx_create.argtypes = [P, P]
+    L.bm_ctx_create.restype = I32
+    L.bm_ctx_submit.argtypes = [P, P, P]
+    L.bm_ctx_submit.restype = I32
+    L.bm_ctx_poll.argtypes = [P, I64, P]
+    L.bm_ctx_poll.restype = I32
+    L.bm_ctx_wait.argtypes = [P, I64, I32, P]
+    L.bm_ctx_wait.restype = I32
+    L.bm_ctx_cancel.argtypes = [P, I64]
+    L.bm_ctx_cancel.restype = I32
+    L.bm_ctx_release.argtypes = [P, I64]
+    L.bm_ctx_release.restype = I32
+    L.bm_ctx_info.argtypes = [P, P]
+    L.bm_ctx_info.restype = I32
+    L.bm_ctx_destroy.argtypes = [P]
+    L.bm_ctx_destroy.restype = I32
     L.bm_gather_rows.argtypes = [P, I64, I32, P, I64, P, P]
     L.bm_gather_rows.restype = I32
     L.kmeans_lloyd_batched.argtypes = [I32, P, I32, P, P, P, P, P, P, P, P]
     L.kmeans_lloyd_batched.restype = I32
     L.bm_debug_batch_info.argtypes = [P, P]
     L.bm_debug_batch_info.restype = I32
+    L.bm_debug_batch_round_ms.argtypes = [I32]
+    L.bm_debug_batch_round_ms.restype = ct.c_double
     L.bm_debug_rechecked.argtypes = []
     L.bm_debug_rechecked.restype = I64
     L.bm_debug_assign_ms.argtypes = []
@@ -275,7 +328,9 @@ def kmeans_lloyd_batched(P, s, k, C, deg, want_labels=True, **opts):
                                   f.ctypes.data_as(ct.c_void_p), passes.ctypes.data_as(ct.c_void_p)))
     rounds, tile = ct.c_int32(0), ct.c_int32(0)
     L.bm_debug_batch_info(ct.byref(rounds), ct.byref(tile))
-    return dg, labels, f, passes, {"rounds": rounds.value, "tile_rows": tile.value}
+    round_ms = [L.bm_debug_batch_round_ms(i) for i in range(rounds.value)]
+    return dg, labels, f, passes, {"rounds": rounds.value, "tile_rows": tile.value,
+                                   "round_ms": round_ms}
 
 
 def prepare_batch(X, solves, n_local_trials=3, **opts):
@@ -300,6 +355,103 @@ def prepare_batch(X, solves, n_local_trials=3, **opts):
         r += sj
         c += kj
     return P, s, k, C, deg
+
+
+class Server:
+    """A serving context (bm_ctx): jobs run concurrently on `slots` workers,
+    admitted in order by device-scratch footprint within hbm_budget."""
+
+    def __init__(self, slots=4, hbm_budget=8 << 30, grid_per_job=0):
+        L = load()
+        cfg = ServeConfig()
+        _check(L.bm_serve_default_config(ct.byref(cfg)))
+        cfg.slots = slots
+        cfg.hbm_budget = hbm_budget
+        cfg.grid_per_job = grid_per_job
+        h = ct.c_void_p()
+        _check(L.bm_ctx_create(ct.byref(cfg), ct.byref(h)))
+        self._h = h
+        self._jobs = {}
+
+    def submit(self, X, k, s, n_samples, seed, want_labels=False, want_sse=True, **opts):
+        """Queue bigmeans_fit(X, ...); returns a job id.  The outputs live in
+        the record until result() is called."""
+        L = load()
+        n, d = X.shape
+        xp, xdt = _x_ptr(X)
+        o = options(x_dtype=xdt, stream=None, **opts)
+        rec = {"X": X, "centroids": torch.empty((k, d), dtype=torch.float32, device=X.device),
+               "labels": torch.empty(n, dtype=torch.int32, device=X.device) if want_labels else None,
+               "deg": np.ones(k, dtype=np.uint8), "sse": ct.c_double(0.0), "stats": Stats(),
+               "sample_f": np.zeros(n_samples, dtype=np.float64)}
+        rec["stats"].struct_size = ct.sizeof(Stats)
+        o.sample_f = rec["sample_f"].ctypes.data
+        j = Job()
+        j.struct_size = ct.sizeof(Job)
+        j.X = xp
+        j.n, j.d, j.k, j.s, j.n_samples, j.seed = n, d, k, s, n_samples, seed
+        j.opt = o
+        j.centroids = rec["centroids"].data_ptr()
+        j.labels = rec["labels"].data_ptr() if want_labels else None
+        j.degenerate = rec["deg"].ctypes.data
+        j.sse = ct.addressof(rec["sse"]) if want_sse or want_labels else None
+        j.stats = ct.addressof(rec["stats"])
+        jid = ct.c_int64(0)
+        _check(L.bm_ctx_submit(self._h, ct.byref(j), ct.byref(jid)))
+        self._jobs[jid.value] = rec
+        return jid.value
+
+    def poll(self, jid):
+        info = JobInfo()
+        info.struct_size = ct.sizeof(JobInfo)
+        _check(load().bm_ctx_poll(self._h, jid, ct.byref(info)))
+        return info
+
+    def wait(self, jid, timeout_ms=-1):
+        info = JobInfo()
+        info.struct_size = ct.sizeof(JobInfo)
+        _check(load().bm_ctx_wait(self._h, jid, timeout_ms, ct.byref(info)))
+        return info
+
+    def cancel(self, jid):
+        _check(load().bm_ctx_cancel(self._h, jid))
+
+    def result(self, jid):
+        """Wait for the job, then return its outputs (dict as bigmeans_fit) and
+        its timing record; the record is released."""
+        info = self.wait(jid)
+        rec = self._jobs.pop(jid)
+        _check(load().bm_ctx_release(self._h, jid))
+        if info.state != BM_JOB_DONE:
+            raise BigmeansError(info.result, info.error.decode(errors="replace"))
+        return {"centroids": rec["centroids"], "degenerate": rec["deg"], "sse": rec["sse"].value,
+                "labels": rec["labels"], "sample_f": rec["sample_f"],
+                "stats": rec["stats"].as_dict(),
+                "t_submit_ms": info.t_submit_ms, "t_start_ms": info.t_start_ms,
+                "t_end_ms": info.t_end_ms, "slot": info.slot, "footprint": info.footprint}
+
+    def info(self):
+        inf = ServeInfo()
+        inf.struct_size = ct.sizeof(ServeInfo)
+        _check(load().bm_ctx_info(self._h, ct.byref(inf)))
+        return inf.as_dict()
+
+    def close(self):
+        if self._h is not None:
+            _check(load().bm_ctx_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def last_rechecked():

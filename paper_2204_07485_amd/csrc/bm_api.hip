@@ -21,6 +21,7 @@ static thread_local int64_t g_last_rechecked = 0;
 static thread_local double g_last_assign_ms = 0.0;
 static thread_local int32_t g_last_batch_rounds = 0;
 static thread_local int32_t g_last_batch_tile = 0;
+static thread_local std::vector<float> g_last_batch_ms;  // device time of each round's graph
 
 bm_status set_error(bm_status code, const char* fmt, ...) {
   va_list ap;
@@ -43,11 +44,30 @@ void clear_error() { g_err[0] = '\0'; }
 // scratch pool: one growing device allocation per device, guarded by a mutex
 
 static std::mutex g_mu;
-struct Pool {
-  void* ptr = nullptr;
-  size_t bytes = 0;
-};
-static Pool g_pool[64];
+static std::mutex g_launch_mu;
+static ScratchPool g_pool[64];
+// A serving slot's worker thread uses its own pool (no shared state, no lock).
+static thread_local ScratchPool* t_pool = nullptr;
+
+void scratch_set_thread_pool(ScratchPool* p) { t_pool = p; }
+
+void scratch_pool_free(ScratchPool* p) {
+  if (p->ptr) (void)hipFree(p->ptr);
+  p->ptr = nullptr;
+  p->bytes = 0;
+}
+
+bm_status scratch_pool_reserve(ScratchPool* p, size_t bytes) {
+  if (p->bytes >= bytes) return BM_OK;
+  scratch_pool_free(p);
+  if (hipMalloc(&p->ptr, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p->ptr = nullptr;
+    return set_error(BM_ENOMEM, "cannot allocate %zu bytes of device scratch", bytes);
+  }
+  p->bytes = bytes;
+  return BM_OK;
+}
 
 void* scratch_get(size_t bytes, hipStream_t stream, bm_status* st) {
   int dev = 0;
@@ -55,7 +75,7 @@ void* scratch_get(size_t bytes, hipStream_t stream, bm_status* st) {
     *st = set_error(BM_EDEVICE, "no current HIP device");
     return nullptr;
   }
-  Pool& p = g_pool[dev];
+  ScratchPool& p = t_pool ? *t_pool : g_pool[dev];
   if (p.bytes >= bytes) {
     *st = BM_OK;
     return p.ptr;
@@ -147,6 +167,7 @@ static bm_status resolve(const bm_options* in, bm_options* out) {
 struct SolverPlan {
   int dm = 0;
   int grid = 0;
+  int gmax = 0;  // co-resident workgroups of this configuration on the device
   int64_t cand_cap = 0;
   uint64_t win_lo = 0, win_hi = 0;
   bool sums_in_lds = false;
@@ -180,6 +201,7 @@ static bm_status plan_solver(int d, int k, int64_t s, int64_t n_points, int grid
   int gmax = 0;
   st = solver_max_grid(sp->dm, sp->lds, &gmax);
   if (st != BM_OK) return st;
+  sp->gmax = gmax;
   int g = grid_req;
   if (g <= 0) {
     const int64_t want = (s + 511) / 512;
@@ -373,27 +395,62 @@ bm_status bm_release_scratch(void) {
   return BM_OK;
 }
 
-bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s,
-                       int32_t n_samples, uint64_t seed, const bm_options* opt_in,
-                       float* centroids, double* sse, int32_t* labels, uint8_t* degenerate,
-                       bm_stats* stats) {
-  clear_error();
-  bm_options o;
-  bm_status st = resolve(opt_in, &o);
+}  // extern "C"
+
+namespace bm {
+
+bm_status fit_validate(const void* X, int64_t n, int32_t d, int32_t k, int64_t s,
+                       int32_t n_samples, const bm_options* opt_in, float* centroids,
+                       uint8_t* degenerate, bm_stats* stats, bm_options* o) {
+  bm_status st = resolve(opt_in, o);
   if (st != BM_OK) return st;
   if ((st = check_sizes(n, d, k, s)) != BM_OK) return st;
   if (n_samples < 1) return set_error(BM_EINVAL, "n_samples must be >= 1");
   if (!X || !centroids) return set_error(BM_EINVAL, "X and centroids are required");
-  if (o.resume && !degenerate) return set_error(BM_EINVAL, "resume needs the degenerate flags");
-  if (static_cast<int64_t>(o.t_start) + n_samples > 4294967295LL)
+  if (o->resume && !degenerate) return set_error(BM_EINVAL, "resume needs the degenerate flags");
+  if (static_cast<int64_t>(o->t_start) + n_samples > 4294967295LL)
     return set_error(BM_EINVAL, "sample indices exceed 2^32");
   if (stats && stats->struct_size != sizeof(bm_stats))
     return set_error(BM_EINVAL, "bm_stats.struct_size mismatch");
-  hipStream_t stream = static_cast<hipStream_t>(o.stream);
+  return BM_OK;
+}
 
-  std::lock_guard<std::mutex> lock(g_mu);
+bm_status solver_coresident_blocks(int d, int k, int64_t s, int64_t n, int* blocks) {
+  SolverPlan sp;
+  const bm_status st = plan_solver(d, k, s, n, 0, &sp);
+  if (st != BM_OK) return st;
+  *blocks = sp.gmax;
+  return BM_OK;
+}
+
+size_t fit_scratch_bytes(int64_t n, int32_t d, int32_t k, int64_t s, int32_t n_samples,
+                         bool final_pass) {
+  uint64_t lo = 0, hi = 0;
+  int64_t cap = 0;
+  sampler_window(n, s, &lo, &hi, &cap);
+  SolverBuffers b;
+  memset(&b.a, 0, sizeof b.a);
+  const int final_grid = final_pass ? 2048 : 0;  // an upper bound of either final kernel's grid
+  layout_solver(nullptr, n, s, d, k, n_samples, cap, true, true, true, true, final_grid, &b);
+  return b.bytes;
+}
+
+// The body of bigmeans_fit after validation.  The caller serialises access to
+// the scratch pool in use (the shared pool under g_mu, or a serving slot's own
+// pool).  grid_cap > 0 bounds the cooperative grid.
+bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int32_t n_samples,
+                  uint64_t seed, const bm_options& o, float* centroids, double* sse,
+                  int32_t* labels, uint8_t* degenerate, bm_stats* stats, int grid_cap) {
+  bm_status st = BM_OK;
+  hipStream_t stream = static_cast<hipStream_t>(o.stream);
+  // Host-side setup and launches of concurrent fits (serving slots) are
+  // serialised; the device work they enqueue still overlaps.
+  std::unique_lock<std::mutex> launch_lock(g_launch_mu);
   SolverPlan sp;
   if ((st = plan_solver(d, k, s, n, o.grid, &sp)) != BM_OK) return st;
+  if (grid_cap > 0 && sp.grid > grid_cap &&
+      (st = plan_solver(d, k, s, n, grid_cap, &sp)) != BM_OK)
+    return st;
 
   const bool final_pass = sse || labels;
   const bool final_mfma = final_pass && o.precision == BM_PREC_BF16_MFMA;
@@ -460,6 +517,7 @@ bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s
                         b.done, b.sse_dev, final_grid, stream);
   }
   BM_HIP(hipEventRecord(ev[2], stream));
+  launch_lock.unlock();
   if (final_pass && fst == BM_OK)
     BM_HIP(hipMemcpyAsync(&sse_host, b.sse_dev, sizeof(double), hipMemcpyDeviceToHost, stream));
 
@@ -508,6 +566,22 @@ bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s
     }
   }
   return BM_OK;
+}
+
+}  // namespace bm
+
+extern "C" {
+
+bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s,
+                       int32_t n_samples, uint64_t seed, const bm_options* opt_in,
+                       float* centroids, double* sse, int32_t* labels, uint8_t* degenerate,
+                       bm_stats* stats) {
+  clear_error();
+  bm_options o;
+  bm_status st = fit_validate(X, n, d, k, s, n_samples, opt_in, centroids, degenerate, stats, &o);
+  if (st != BM_OK) return st;
+  std::lock_guard<std::mutex> lock(g_mu);
+  return fit_run(X, n, d, k, s, n_samples, seed, o, centroids, sse, labels, degenerate, stats, 0);
 }
 
 bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, const uint8_t* deg,
@@ -912,12 +986,21 @@ bm_status kmeans_lloyd_batched(int32_t n_solves, const float* P, int32_t d, cons
   BM_HIPB(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   int still = 1;
   int rounds = 0;
+  hipEvent_t r0 = nullptr, r1 = nullptr;
+  BM_HIPB(hipEventCreate(&r0));
+  BM_HIPB(hipEventCreate(&r1));
+  g_last_batch_ms.clear();
   for (; rounds <= o.max_iter && still; ++rounds) {
     BM_HIPB(hipMemsetAsync(running, 0, sizeof(int), stream));
+    BM_HIPB(hipEventRecord(r0, stream));
     BM_HIPB(hipGraphLaunch(exec, stream));
+    BM_HIPB(hipEventRecord(r1, stream));
     BM_HIPB(hipMemcpyAsync(&still, running, sizeof(int), hipMemcpyDeviceToHost, stream));
     BM_HIPB(hipStreamSynchronize(stream));
+    g_last_batch_ms.push_back(elapsed_ms(r0, r1));
   }
+  (void)hipEventDestroy(r0);
+  (void)hipEventDestroy(r1);
   if (still) return fail(set_error(BM_EDEVICE, "batched Lloyd did not finish in max_iter + 1 rounds"));
   BM_HIPB(hipMemcpyAsync(hs.data(), sv_d, sizeof(BatchSolve) * n_solves, hipMemcpyDeviceToHost, stream));
   BM_HIPB(hipMemcpyAsync(deg, deg_d, static_cast<size_t>(ktot), hipMemcpyDeviceToHost, stream));
@@ -942,6 +1025,11 @@ int32_t bm_debug_batch_info(int32_t* rounds, int32_t* tile_rows) {
   if (rounds) *rounds = g_last_batch_rounds;
   if (tile_rows) *tile_rows = g_last_batch_tile;
   return BM_OK;
+}
+
+// Device time (ms) of round i of the last kmeans_lloyd_batched (0 if out of range).
+double bm_debug_batch_round_ms(int32_t i) {
+  return (i >= 0 && static_cast<size_t>(i) < g_last_batch_ms.size()) ? g_last_batch_ms[i] : 0.0;
 }
 
 }  // extern "C"

@@ -106,9 +106,29 @@ struct SolverArgs {
   int32_t* err;
 };
 
-// Device scratch pool (per process, current device); grows on demand.
+// Device scratch pool (per process, current device); grows on demand.  A
+// thread may switch to a pool of its own (serving slots); nullptr restores the
+// shared pool.
+struct ScratchPool {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
 void* scratch_get(size_t bytes, hipStream_t stream, bm_status* st);
 void scratch_release();
+void scratch_set_thread_pool(ScratchPool* p);
+void scratch_pool_free(ScratchPool* p);
+bm_status scratch_pool_reserve(ScratchPool* p, size_t bytes);  // exactly `bytes` if it grows
+
+// bigmeans_fit in parts (bm_api.hip), for the serving engine.
+bm_status fit_validate(const void* X, int64_t n, int32_t d, int32_t k, int64_t s,
+                       int32_t n_samples, const bm_options* opt_in, float* centroids,
+                       uint8_t* degenerate, bm_stats* stats, bm_options* o);
+size_t fit_scratch_bytes(int64_t n, int32_t d, int32_t k, int64_t s, int32_t n_samples,
+                         bool final_pass);
+bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int32_t n_samples,
+                  uint64_t seed, const bm_options& o, float* centroids, double* sse,
+                  int32_t* labels, uint8_t* degenerate, bm_stats* stats, int grid_cap);
+bm_status solver_coresident_blocks(int d, int k, int64_t s, int64_t n, int* blocks);
 
 // Error reporting for the ABI layer.
 bm_status set_error(bm_status code, const char* fmt, ...);

@@ -137,3 +137,26 @@ def test_batched_and_gather_reject_invalid_arguments(bm):
     assert lib.bm_gather_rows(ct.c_void_p(16), 10, 2, None, 5, P, None) == bm.BM_EINVAL
     assert lib.bm_gather_rows(ct.c_void_p(16), 10, 0, idx, 5, P, None) == bm.BM_EINVAL
     assert lib.bm_last_error()
+
+
+def test_serving_rejects_invalid_arguments(bm):
+    lib = bm.load()
+    cfg = bm.ServeConfig()
+    assert lib.bm_serve_default_config(ct.byref(cfg)) == 0
+    assert cfg.slots == 4 and cfg.struct_size == ct.sizeof(bm.ServeConfig)
+    h = ct.c_void_p()
+    for field, value in (("slots", 0), ("slots", 65), ("hbm_budget", 1000), ("grid_per_job", -1),
+                         ("struct_size", 2)):
+        c2 = bm.ServeConfig()
+        lib.bm_serve_default_config(ct.byref(c2))
+        setattr(c2, field, value)
+        assert lib.bm_ctx_create(ct.byref(c2), ct.byref(h)) == bm.BM_EINVAL, field
+    assert lib.bm_ctx_create(ct.byref(cfg), None) == bm.BM_EINVAL
+    jid = ct.c_int64()
+    assert lib.bm_ctx_submit(None, None, ct.byref(jid)) == bm.BM_EINVAL
+    info = bm.JobInfo()
+    info.struct_size = ct.sizeof(bm.JobInfo)
+    assert lib.bm_ctx_poll(None, 1, ct.byref(info)) == bm.BM_EINVAL
+    assert lib.bm_ctx_wait(None, 1, 0, None) == bm.BM_EINVAL
+    assert lib.bm_ctx_cancel(None, 1) == bm.BM_EINVAL
+    assert lib.bm_ctx_destroy(None) == bm.BM_OK

@@ -1,0 +1,110 @@
+"""GPU tests of the serving context (bm_ctx): a job run in a mix of
+concurrent jobs gives the result it gives alone (same samples, so the same
+per-sample objectives, degenerate flags and final objective, to the parity
+tolerance), admission keeps the scratch held within the budget, and
+cancellation, timeouts and failures are reported per job while the context
+keeps serving."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2204_07485_amd import synth
+from tests.parity import assert_sse
+
+pytestmark = pytest.mark.gpu
+
+KW = dict(max_iter=300, tol=1e-4, stop_rule=1, n_local_trials=3)
+
+
+def _jobs(count, seed=5, n_range=(1e4, 2e5)):
+    out = []
+    for job in synth.serve_jobs(count, seed=seed, n_range=n_range):
+        X = torch.from_numpy(synth.serve_job_data(job)).cuda()
+        out.append((job, X))
+    return out
+
+
+def test_mix_equals_alone():
+    from paper_2204_07485_amd import bigmeans
+    jobs = _jobs(12)
+    with bigmeans.Server(slots=4) as srv:
+        ids = [srv.submit(X, j["k"], j["s"], j["n_samples"], j["seed"], **KW) for j, X in jobs]
+        res = [srv.result(i) for i in ids]
+        grid = srv.info()["grid_per_job"]
+        info = srv.info()
+    assert info["completed"] == len(jobs) and info["failed"] == 0
+    overlap = 0
+    for a in range(len(res)):
+        for b in range(a + 1, len(res)):
+            if res[a]["t_start_ms"] < res[b]["t_end_ms"] and res[b]["t_start_ms"] < res[a]["t_end_ms"]:
+                overlap += 1
+    assert overlap > 0, "no two jobs ran at the same time"
+    for (j, X), r in zip(jobs, res):
+        print(f"job {j['id']}: n={j['n']} d={j['d']} k={j['k']}", flush=True)
+        alone = bigmeans.bigmeans_fit(X, j["k"], j["s"], j["n_samples"], j["seed"], grid=grid, **KW)
+        assert np.array_equal(r["degenerate"], alone["degenerate"])
+        np.testing.assert_allclose(r["sample_f"], alone["sample_f"], rtol=1e-6)
+        assert_sse(r["sse"], alone["sse"])
+        assert r["stats"]["samples"] == alone["stats"]["samples"]
+
+
+def test_budget_bounds_the_scratch_held():
+    from paper_2204_07485_amd import bigmeans
+    jobs = _jobs(8, seed=6)
+    # a budget that holds the largest job but not two of the largest
+    with bigmeans.Server(slots=4, hbm_budget=1 << 40) as srv:
+        ids = [srv.submit(X, j["k"], j["s"], j["n_samples"], j["seed"], **KW) for j, X in jobs]
+        big = max(srv.poll(i).footprint for i in ids)
+        for i in ids:
+            srv.result(i)
+    budget = int(big * 1.5)
+    with bigmeans.Server(slots=4, hbm_budget=budget) as srv:
+        ids = [srv.submit(X, j["k"], j["s"], j["n_samples"], j["seed"], **KW) for j, X in jobs]
+        res = [srv.result(i) for i in ids]
+        info = srv.info()
+    assert info["completed"] == len(jobs)
+    assert info["peak_reserved_bytes"] <= budget
+    # jobs started in submission order
+    starts = [r["t_start_ms"] for r in res]
+    assert starts == sorted(starts)
+
+
+def test_cancel_timeout_and_oversized_job():
+    from paper_2204_07485_amd import bigmeans
+    jobs = _jobs(5, seed=7)
+    with bigmeans.Server(slots=1) as srv:
+        ids = [srv.submit(X, j["k"], j["s"], j["n_samples"], j["seed"], **KW) for j, X in jobs]
+        last = ids[-1]
+        with pytest.raises(bigmeans.BigmeansError) as e:
+            srv.wait(last, timeout_ms=0)
+        assert e.value.code == bigmeans.BM_ETIMEDOUT
+        srv.cancel(last)
+        assert srv.poll(last).state == bigmeans.BM_JOB_CANCELLED
+        with pytest.raises(bigmeans.BigmeansError) as e:
+            srv.result(last)
+        assert e.value.code == bigmeans.BM_ECANCELLED
+        for i in ids[:-1]:
+            assert srv.result(i)["sse"] > 0
+        with pytest.raises(bigmeans.BigmeansError):
+            srv.cancel(ids[0])  # finished: no longer cancellable
+    with bigmeans.Server(slots=2, hbm_budget=2 << 20) as srv:
+        j, X = jobs[0]
+        with pytest.raises(bigmeans.BigmeansError) as e:
+            srv.submit(X, j["k"], j["s"], j["n_samples"], j["seed"], **KW)
+        assert e.value.code == bigmeans.BM_ENOMEM
+
+
+def test_failed_job_is_reported_and_serving_continues():
+    from paper_2204_07485_amd import bigmeans
+    jobs = _jobs(3, seed=8)
+    with bigmeans.Server(slots=2) as srv:
+        j, X = jobs[0]
+        bad = srv.submit(X, j["k"], j["s"], j["n_samples"], j["seed"], spin_limit=1, **KW)
+        good = [srv.submit(X2, j2["k"], j2["s"], j2["n_samples"], j2["seed"], **KW)
+                for j2, X2 in jobs[1:]]
+        info = srv.wait(bad)
+        assert info.state == bigmeans.BM_JOB_FAILED
+        assert info.result == bigmeans.BM_EDEVICE and info.error
+        for i in good:
+            assert srv.result(i)["sse"] > 0
+        assert srv.info()["failed"] == 1
