@@ -228,34 +228,37 @@ struct SolverBuffers {
 
 // Lay out every solver buffer; with base == nullptr only the size is computed.
 static void layout_solver(char* base, int64_t n, int64_t s, int d, int k, int T, int64_t cand_cap, bool own_P,
-                          bool own_idx, bool own_labels, bool own_inc, int final_grid,
+                          bool own_idx, bool own_labels, bool own_inc, int final_grid, int sbatch,
                           SolverBuffers* b) {
   Layout L;
   L.base = base;
   SolverArgs& a = b->a;
+  const size_t B = static_cast<size_t>(sbatch);
+  a.sbatch = sbatch;
   a.bar = L.take<GridBarrier>(1);
   a.err = L.take<int32_t>(1);
   a.counters = L.take<int64_t>(kNumCounters);
-  a.cand_count = L.take<uint32_t>(1);
+  a.cand_count = L.take<uint32_t>(B);
   a.hist = L.take<uint32_t>(3 * 256);
   a.sums = L.take<double>(3 * static_cast<size_t>(kReplicas) * k * d);
   a.cnt = L.take<int32_t>(3 * static_cast<size_t>(kReplicas) * k);
   b->ctrl_bytes = L.off;
   a.c64 = L.take<double>(2 * static_cast<size_t>(k) * d);
-  a.thr = L.take<uint64_t>(2);
+  a.thr = L.take<uint64_t>(2 * B);
+  a.smiss = L.take<int32_t>(B);
   a.sse_part = L.take<double>(2 * kMaxGrid);
   a.wsum = L.take<double>(kMaxGrid);
   a.phi_part = L.take<double>(static_cast<size_t>(kMaxGrid) * kMaxTrials);
   a.cand = L.take<int64_t>(kMaxTrials);
-  a.wg_lo = L.take<uint32_t>(kMaxGrid);
-  a.wg_off = L.take<uint32_t>(kMaxGrid);
-  a.cand_key = L.take<uint64_t>(cand_cap);
-  a.cand_idx = L.take<int32_t>(cand_cap);
-  a.selcode = L.take<uint8_t>(n);
+  a.wg_lo = L.take<uint32_t>(B * kMaxGrid);
+  a.wg_off = L.take<uint32_t>(B * kMaxGrid);
+  a.cand_key = L.take<uint64_t>(B * static_cast<size_t>(cand_cap));
+  a.cand_idx = L.take<int32_t>(B * static_cast<size_t>(cand_cap));
+  a.selcode = L.take<uint8_t>(B * ((static_cast<size_t>(n) + 15) & ~size_t(15)));  // 16-byte slots
   a.w = L.take<double>(s);
   a.sample_f = L.take<double>(T > 0 ? T : 1);
-  float* P = L.take<float>(own_P ? static_cast<size_t>(s) * d : 1);
-  int32_t* idx = L.take<int32_t>(own_idx ? s : 1);
+  float* P = L.take<float>(own_P ? B * static_cast<size_t>(s) * d : 1);
+  int32_t* idx = L.take<int32_t>(own_idx ? B * static_cast<size_t>(s) : 1);
   int32_t* lab = L.take<int32_t>(own_labels ? s : 1);
   float* Cinc = L.take<float>(own_inc ? static_cast<size_t>(k) * d : 1);
   uint8_t* deg = L.take<uint8_t>(k);
@@ -276,14 +279,16 @@ static void layout_solver(char* base, int64_t n, int64_t s, int d, int k, int T,
 static bm_status prepare_solver(hipStream_t stream, int64_t n, int64_t s, int d, int k, int T,
                                 int64_t cand_cap,
                                 bool own_P, bool own_idx, bool own_labels, bool own_inc,
-                                int final_grid, SolverBuffers* b) {
+                                int final_grid, int sbatch, SolverBuffers* b) {
   SolverArgs keep = b->a;
-  layout_solver(nullptr, n, s, d, k, T, cand_cap, own_P, own_idx, own_labels, own_inc, final_grid, b);
+  layout_solver(nullptr, n, s, d, k, T, cand_cap, own_P, own_idx, own_labels, own_inc, final_grid,
+                sbatch, b);
   bm_status st = BM_OK;
   char* base = static_cast<char*>(scratch_get(b->bytes, stream, &st));
   if (!base) return st;
   b->a = keep;
-  layout_solver(base, n, s, d, k, T, cand_cap, own_P, own_idx, own_labels, own_inc, final_grid, b);
+  layout_solver(base, n, s, d, k, T, cand_cap, own_P, own_idx, own_labels, own_inc, final_grid,
+                sbatch, b);
   BM_HIP(hipMemsetAsync(base, 0, b->ctrl_bytes, stream));
   if (final_grid > 0) {
     BM_HIP(hipMemsetAsync(b->done, 0, sizeof(unsigned int), stream));
@@ -431,7 +436,8 @@ size_t fit_scratch_bytes(int64_t n, int32_t d, int32_t k, int64_t s, int32_t n_s
   SolverBuffers b;
   memset(&b.a, 0, sizeof b.a);
   const int final_grid = final_pass ? 2048 : 0;  // an upper bound of either final kernel's grid
-  layout_solver(nullptr, n, s, d, k, n_samples, cap, true, true, true, true, final_grid, &b);
+  layout_solver(nullptr, n, s, d, k, n_samples, cap, true, true, true, true, final_grid,
+                sample_slots(n, s, d, n_samples, cap), &b);
   return b.bytes;
 }
 
@@ -459,7 +465,7 @@ bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int
   SolverBuffers b;
   memset(&b.a, 0, sizeof b.a);
   if ((st = prepare_solver(stream, n, s, d, k, n_samples, sp.cand_cap, true, true, true, true,
-                           final_grid, &b)) != BM_OK)
+                           final_grid, sample_slots(n, s, d, n_samples, sp.cand_cap), &b)) != BM_OK)
     return st;
   SolverArgs& a = b.a;
   a.X = X;
@@ -674,7 +680,7 @@ static bm_status run_solver_on_sample(const float* P, int64_t s, int32_t d, int3
   b.a.Cinc = C;
   b.a.labels = labels;
   if ((st = prepare_solver(stream, s, s, d, k, 1, sp.cand_cap, false, true, labels == nullptr, false,
-                           0, &b)) != BM_OK)
+                           0, 1, &b)) != BM_OK)
     return st;
   SolverArgs& a = b.a;
   a.X = nullptr;
@@ -757,7 +763,7 @@ bm_status bm_sample_indices(int64_t n, int64_t s, uint64_t seed, int32_t t, int3
   SolverBuffers b;
   memset(&b.a, 0, sizeof b.a);
   b.a.idx = idx;
-  if ((st = prepare_solver(stream, n, s, 1, 1, 1, sp.cand_cap, false, false, true, true, 0, &b)) != BM_OK)
+  if ((st = prepare_solver(stream, n, s, 1, 1, 1, sp.cand_cap, false, false, true, true, 0, 1, &b)) != BM_OK)
     return st;
   SolverArgs& a = b.a;
   a.n = n;

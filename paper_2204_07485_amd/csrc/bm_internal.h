@@ -72,9 +72,10 @@ struct SolverArgs {
   uint64_t win_lo;           // predicted key window of the sampler (inclusive)
   uint64_t win_hi;
   uint32_t spin_limit;
-  // sample-sized buffers
-  float* P;                  // s x d
-  int32_t* idx;              // s
+  int32_t sbatch;            // samples drawn per batch (slots of the buffers below)
+  // sample-sized buffers (sbatch slots of each when sampling)
+  float* P;                  // sbatch x s x d
+  int32_t* idx;              // sbatch x s
   int32_t* labels;           // s
   double* w;                 // s (K-means++ D^2 weights)
   // incumbent
@@ -91,13 +92,14 @@ struct SolverArgs {
   int64_t* cand;             // kMaxTrials
   // sampler
   uint32_t* hist;            // 3 x 256 ring
-  uint32_t* wg_lo;           // kMaxGrid
-  uint32_t* wg_off;          // kMaxGrid
-  uint64_t* cand_key;        // cand_cap
-  int32_t* cand_idx;         // cand_cap
-  uint32_t* cand_count;      // 1
-  uint8_t* selcode;          // n: point below (1), inside (2), above (0) the key window
-  uint64_t* thr;             // 2: threshold key, index
+  uint32_t* wg_lo;           // sbatch x kMaxGrid
+  uint32_t* wg_off;          // sbatch x kMaxGrid
+  uint64_t* cand_key;        // sbatch x cand_cap
+  int32_t* cand_idx;         // sbatch x cand_cap
+  uint32_t* cand_count;      // sbatch
+  uint8_t* selcode;          // sbatch x n: key below (1), inside (2), above (0) the window
+  uint64_t* thr;             // sbatch x 2: threshold key, index
+  int32_t* smiss;            // sbatch: the predicted window missed
   // outputs / control
   int32_t* sample_idx_out;   // T x s or null
   double* sample_f;          // T
@@ -137,6 +139,10 @@ void clear_error();
 // Launchers (defined in bm_solver.hip / bm_assign.hip).
 size_t solver_lds_bytes(int dm, int k, int d, bool sums_in_lds, bool c64_in_lds);
 void sampler_window(int64_t n, int64_t s, uint64_t* lo, uint64_t* hi, int64_t* cap);
+// Samples drawn per batch by bigmeans_fit: all T when their buffers (rows,
+// indices, codes, candidates) fit in kSampleBatchBytes, else fewer (>= 1).
+constexpr double kSampleBatchBytes = 256.0 * 1024 * 1024;
+int sample_slots(int64_t n, int64_t s, int d, int T, int64_t cand_cap);
 int padded_dim(int d);
 bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t stream);
 bm_status solver_max_grid(int dm, size_t lds, int* max_grid);

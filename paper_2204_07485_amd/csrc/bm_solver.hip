@@ -153,12 +153,46 @@ __device__ __forceinline__ bool pair_le(uint64_t k, int64_t i, uint64_t tk, int6
   return k < tk || (k == tk && i <= ti);
 }
 
+// Buffers of one sample slot.  Samples are drawn in batches of a.sbatch
+// (they depend only on (seed, t)); slot b holds the b-th sample of a batch.
+// Bytes between the code arrays of two slots (16-byte aligned slots, so the
+// two codes of a point pair are one aligned 16-bit store).
+__host__ __device__ __forceinline__ size_t code_stride(int64_t n) {
+  return (static_cast<size_t>(n) + 15) & ~size_t(15);
+}
+
+struct SBuf {
+  float* P;              // s x d gathered rows (null when rows are not gathered)
+  int32_t* idx;          // s sampled indices
+  uint8_t* selcode;      // n: key below (1), inside (2), above (0) the window
+  uint64_t* cand_key;    // cand_cap
+  int32_t* cand_idx;     // cand_cap
+  uint32_t* cand_count;  // 1
+  uint32_t* wg_lo;       // kMaxGrid
+  uint32_t* wg_off;      // kMaxGrid
+  uint64_t* thr;         // 2: threshold key, index
+};
+
+__device__ __forceinline__ SBuf slot_bufs(const SolverArgs& a, float* Pb, int32_t* idxb, int b) {
+  SBuf q;
+  q.P = Pb ? Pb + static_cast<size_t>(b) * a.s * a.d : nullptr;
+  q.idx = idxb + static_cast<size_t>(b) * a.s;
+  q.selcode = a.selcode + static_cast<size_t>(b) * code_stride(a.n);
+  q.cand_key = a.cand_key + static_cast<size_t>(b) * a.cand_cap;
+  q.cand_idx = a.cand_idx + static_cast<size_t>(b) * a.cand_cap;
+  q.cand_count = a.cand_count + b;
+  q.wg_lo = a.wg_lo + static_cast<size_t>(b) * kMaxGrid;
+  q.wg_off = a.wg_off + static_cast<size_t>(b) * kMaxGrid;
+  q.thr = a.thr + 2 * static_cast<size_t>(b);
+  return q;
+}
+
 // Append (key, index) to this workgroup's candidate buffer in LDS (one LDS
 // atomic per wavefront); entries beyond the buffer go straight to the global
 // list.  flush_candidates moves the buffer to the global list with a single
 // global atomic per workgroup.
-__device__ __forceinline__ void append_candidate(const SolverArgs& a, const LdsPlan& pl, Lds& L,
-                                                 bool pred, uint64_t key, int64_t i) {
+__device__ __forceinline__ void append_candidate(const SolverArgs& a, const SBuf& sb, const LdsPlan& pl,
+                                                 Lds& L, bool pred, uint64_t key, int64_t i) {
   const unsigned long long mask = __ballot(pred);
   if (mask == 0ull) return;
   const int lane = threadIdx.x & (kWave - 1);
@@ -173,41 +207,44 @@ __device__ __forceinline__ void append_candidate(const SolverArgs& a, const LdsP
       reinterpret_cast<uint64_t*>(L.B + pl.ckey)[slot] = key;
       reinterpret_cast<int32_t*>(L.B + pl.cidx)[slot] = static_cast<int32_t>(i);
     } else {
-      const unsigned int gs = atomicAdd(a.cand_count, 1u);
+      const unsigned int gs = atomicAdd(sb.cand_count, 1u);
       if (gs < static_cast<unsigned int>(a.cand_cap)) {
-        a.cand_key[gs] = key;
-        a.cand_idx[gs] = static_cast<int32_t>(i);
+        sb.cand_key[gs] = key;
+        sb.cand_idx[gs] = static_cast<int32_t>(i);
       }
     }
   }
 }
 
-__device__ __forceinline__ void flush_candidates(const SolverArgs& a, const LdsPlan& pl, Lds& L) {
+__device__ __forceinline__ void flush_candidates(const SolverArgs& a, const SBuf& sb, const LdsPlan& pl,
+                                                 Lds& L) {
   __syncthreads();
   const unsigned int cnt = static_cast<unsigned int>(L.misc[4]);
   const unsigned int nl = cnt < static_cast<unsigned int>(kCandStage) ? cnt : kCandStage;
-  if (threadIdx.x == 0) L.misc[5] = nl ? static_cast<int>(atomicAdd(a.cand_count, nl)) : 0;
+  if (threadIdx.x == 0) L.misc[5] = nl ? static_cast<int>(atomicAdd(sb.cand_count, nl)) : 0;
   __syncthreads();
   const unsigned int gb = static_cast<unsigned int>(L.misc[5]);
   const uint64_t* ck = reinterpret_cast<const uint64_t*>(L.B + pl.ckey);
   const int32_t* ci = reinterpret_cast<const int32_t*>(L.B + pl.cidx);
   for (unsigned int r = threadIdx.x; r < nl; r += kBlock) {
     if (gb + r < static_cast<unsigned int>(a.cand_cap)) {
-      a.cand_key[gb + r] = ck[r];
-      a.cand_idx[gb + r] = ci[r];
+      sb.cand_key[gb + r] = ck[r];
+      sb.cand_idx[gb + r] = ci[r];
     }
   }
+  __syncthreads();  // the LDS stage is reused by the next collect pass
 }
 
 // Write sampled point i at position pos: index, and its row gathered into P
 // (the whole row is loaded into registers first, so its loads overlap).
 template <int DM>
-__device__ __forceinline__ void emit_point(const SolverArgs& a, int tt, int64_t pos, int64_t i) {
+__device__ __forceinline__ void emit_point(const SolverArgs& a, const SBuf& sb, int tt, int64_t pos,
+                                           int64_t i) {
   if (pos < 0 || pos >= a.s) {  // inconsistent bookkeeping: never write out of bounds
     atomicCAS(a.err, 0, kErrSelect);
     return;
   }
-  a.idx[pos] = static_cast<int32_t>(i);
+  sb.idx[pos] = static_cast<int32_t>(i);
   if (a.sample_idx_out) a.sample_idx_out[static_cast<size_t>(tt) * a.s + pos] = static_cast<int32_t>(i);
   if (a.do_gather) {
     const int d = a.d;
@@ -216,7 +253,7 @@ __device__ __forceinline__ void emit_point(const SolverArgs& a, int tt, int64_t 
       load_row_bf16<DM>(static_cast<const uint16_t*>(a.X) + static_cast<size_t>(i) * d, d, x);
     else
       load_row_f32<DM>(static_cast<const float*>(a.X) + static_cast<size_t>(i) * d, d, x);
-    float* dst = a.P + static_cast<size_t>(pos) * d;
+    float* dst = sb.P + static_cast<size_t>(pos) * d;
     if ((d & 3) == 0) {
 #pragma unroll
       for (int q = 0; q < DM / 4; ++q)
@@ -230,13 +267,13 @@ __device__ __forceinline__ void emit_point(const SolverArgs& a, int tt, int64_t 
   }
 }
 
-// WG 0: the need-th smallest (key, index) pair among the m collected
-// candidates (exact MSB radix select over 8-bit digits, candidates read from
-// global memory), then the output offset of every workgroup.  Every key below
-// the window is selected, so workgroup g emits wg_lo[g] plus its candidates
-// that do not exceed the threshold pair.
-__device__ __forceinline__ bool select_threshold(const SolverArgs& a, const LdsPlan& pl, Lds& L, int64_t below,
-                                 int64_t m, int64_t ppw) {
+// One workgroup: the need-th smallest (key, index) pair among the m collected
+// candidates of a sample (exact MSB radix select over 8-bit digits), then the
+// output offset of every workgroup.  Every key below the window is selected,
+// so workgroup g emits wg_lo[g] plus its candidates that do not exceed the
+// threshold pair.
+__device__ __forceinline__ bool select_threshold(const SolverArgs& a, const SBuf& sb, const LdsPlan& pl,
+                                                 Lds& L, int64_t below, int64_t m, int64_t ppw) {
   const int tid = threadIdx.x;
   const int G = gridDim.x;
   unsigned int* hist = reinterpret_cast<unsigned int*>(L.B + pl.hist);
@@ -248,15 +285,15 @@ __device__ __forceinline__ bool select_threshold(const SolverArgs& a, const LdsP
   }
   // candidates read from LDS when they fit the stage, else from global memory
   const bool staged = m <= kCandStage;
-  const uint64_t* ckey = staged ? reinterpret_cast<const uint64_t*>(L.B + pl.ckey) : a.cand_key;
-  const int32_t* cidx = staged ? reinterpret_cast<const int32_t*>(L.B + pl.cidx) : a.cand_idx;
+  const uint64_t* ckey = staged ? reinterpret_cast<const uint64_t*>(L.B + pl.ckey) : sb.cand_key;
+  const int32_t* cidx = staged ? reinterpret_cast<const int32_t*>(L.B + pl.cidx) : sb.cand_idx;
   if (staged) {
     uint64_t* sk = reinterpret_cast<uint64_t*>(L.B + pl.ckey);
     int32_t* si = reinterpret_cast<int32_t*>(L.B + pl.cidx);
 #pragma unroll 4
     for (int64_t r = tid; r < m; r += kBlock) {
-      sk[r] = a.cand_key[r];
-      si[r] = a.cand_idx[r];
+      sk[r] = sb.cand_key[r];
+      si[r] = sb.cand_idx[r];
     }
     __syncthreads();
   }
@@ -327,18 +364,18 @@ __device__ __forceinline__ bool select_threshold(const SolverArgs& a, const LdsP
   __syncthreads();
   // output offset of every workgroup: exclusive scan of (selected candidates
   // + keys below the window), two workgroups per thread
-  for (int gg = tid; gg < G; gg += kBlock) selc[gg] += a.wg_lo[gg];
+  for (int gg = tid; gg < G; gg += kBlock) selc[gg] += sb.wg_lo[gg];
   __syncthreads();
   const int g0 = 2 * tid;
   const int v0 = (g0 < G) ? static_cast<int>(selc[g0]) : 0;
   const int v1 = (g0 + 1 < G) ? static_cast<int>(selc[g0 + 1]) : 0;
   int total = 0;
   const int ex = block_exclusive_scan<kBlock, int>(v0 + v1, L.tmpi, total);
-  if (g0 < G) a.wg_off[g0] = static_cast<uint32_t>(ex);
-  if (g0 + 1 < G) a.wg_off[g0 + 1] = static_cast<uint32_t>(ex + v0);
+  if (g0 < G) sb.wg_off[g0] = static_cast<uint32_t>(ex);
+  if (g0 + 1 < G) sb.wg_off[g0 + 1] = static_cast<uint32_t>(ex + v0);
   if (tid == 0) {
-    a.thr[0] = tk;
-    a.thr[1] = static_cast<uint64_t>(ti);
+    sb.thr[0] = tk;
+    sb.thr[1] = static_cast<uint64_t>(ti);
     if (total != a.s) set_err(a, kErrSelect);
     L.misc[2] = (total == a.s) ? 1 : 0;
   }
@@ -350,8 +387,8 @@ __device__ __forceinline__ bool select_threshold(const SolverArgs& a, const LdsP
 // [lo, hi] (inclusive) into wg_lo[g], append the keys inside to the candidate
 // list, and record per point whether its key is below (1), inside (2) or
 // above (0) the window.  Each thread takes a contiguous run of pairs.
-__device__ __forceinline__ void collect_pass(const SolverArgs& a, const LdsPlan& pl, Lds& L,
-                                             uint32_t t, int64_t p0, int64_t p1, uint64_t lo,
+__device__ __forceinline__ void collect_pass(const SolverArgs& a, const SBuf& sb, const LdsPlan& pl,
+                                             Lds& L, uint32_t t, int64_t p0, int64_t p1, uint64_t lo,
                                              uint64_t hi) {
   const int tid = threadIdx.x;
   const int64_t n = a.n;
@@ -371,138 +408,117 @@ __device__ __forceinline__ void collect_pass(const SolverArgs& a, const LdsPlan&
     const int c1 = !v1 ? 0 : (k1 < lo ? 1 : (k1 <= hi ? 2 : 0));
     lo_count += (c0 == 1) + (c1 == 1);
     if (v1) {
-      reinterpret_cast<uint16_t*>(a.selcode)[p] = static_cast<uint16_t>(c0 | (c1 << 8));
+      reinterpret_cast<uint16_t*>(sb.selcode)[p] = static_cast<uint16_t>(c0 | (c1 << 8));
     } else if (v0) {
-      a.selcode[2 * p] = static_cast<uint8_t>(c0);
+      sb.selcode[2 * p] = static_cast<uint8_t>(c0);
     }
-    append_candidate(a, pl, L, c0 == 2, k0, 2 * p);
-    append_candidate(a, pl, L, c1 == 2, k1, 2 * p + 1);
+    append_candidate(a, sb, pl, L, c0 == 2, k0, 2 * p);
+    append_candidate(a, sb, pl, L, c1 == 2, k1, 2 * p + 1);
   }
-  flush_candidates(a, pl, L);
+  flush_candidates(a, sb, pl, L);
   const int wg_lo = block_sum_i32<kBlock>(lo_count, L.tmpi);
-  if (tid == 0) a.wg_lo[blockIdx.x] = static_cast<uint32_t>(wg_lo);
+  if (tid == 0) sb.wg_lo[blockIdx.x] = static_cast<uint32_t>(wg_lo);
 }
 
-// Sample t: the s smallest (key, index) pairs, emitted in index order with
-// their rows gathered into P.  The key window [win_lo, win_hi] predicted from
-// the order statistics of uniform keys (the s-th smallest of n lies within
-// 8 standard deviations of s/n of the key range, plus a margin) almost always
-// holds the threshold, so one collect pass suffices; otherwise MSB histogram
-// passes narrow an exact window first.
-template <int DM>
-__device__ __forceinline__ bool sample_phase(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint32_t t, int tt,
-                             int64_t& hist_passes) {
+// Number of keys below the window over all workgroups (fixed order).
+__device__ __forceinline__ int64_t keys_below(const SBuf& sb, Lds& L) {
+  const int G = gridDim.x;
+  const int g0 = 2 * threadIdx.x;
+  int v = 0;
+  if (g0 < G) v += static_cast<int>(sb.wg_lo[g0]);
+  if (g0 + 1 < G) v += static_cast<int>(sb.wg_lo[g0 + 1]);
+  return block_sum_i32<kBlock>(v, L.tmpi);
+}
+
+// Exact selection for a sample whose predicted window missed the threshold
+// (rare): MSB histogram passes over all keys narrow an exact window, then a
+// collect pass and the selection by workgroup 0.  All workgroups call it.
+__device__ __forceinline__ bool exact_select(const SolverArgs& a, const SBuf& sb, const LdsPlan& pl,
+                                             Lds& L, uint32_t t, int64_t p0, int64_t p1, int64_t ppw,
+                                             int64_t& hist_passes) {
   const int tid = threadIdx.x;
   const int g = blockIdx.x;
-  const int G = gridDim.x;
   const int64_t n = a.n;
-  const int64_t npairs = (n + 1) >> 1;
-  const int64_t ppw = (npairs + G - 1) / G;
-  const int64_t p0 = imin64(npairs, static_cast<int64_t>(g) * ppw);
-  const int64_t p1 = imin64(npairs, p0 + ppw);
   unsigned int* hist = reinterpret_cast<unsigned int*>(L.B + pl.hist);
-
-  // fast path: predicted window
-  const uint64_t s0 = wall_clock64();
-  collect_pass(a, pl, L, t, p0, p1, a.win_lo, a.win_hi);
-  const uint64_t s1 = wall_clock64();
-  if (!sync_grid(a)) return false;
-  const uint64_t s2 = wall_clock64();
-  if (g == 0 && tid == 0) {
-    a.counters[kCntTicksCollect] += static_cast<int64_t>(s1 - s0);
-    a.counters[kCntTicksCollectWait] += static_cast<int64_t>(s2 - s1);
-  }
-  {
-    const int g0 = 2 * tid;
-    int v = 0;
-    if (g0 < G) v += static_cast<int>(a.wg_lo[g0]);
-    if (g0 + 1 < G) v += static_cast<int>(a.wg_lo[g0 + 1]);
-    const int64_t below = block_sum_i32<kBlock>(v, L.tmpi);
-    const int64_t m = __hip_atomic_load(a.cand_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const bool hit = m <= a.cand_cap && below < a.s && a.s <= below + m;
-    if (g == 0) {
-      if (hit && !select_threshold(a, pl, L, below, m, ppw)) return false;
-      if (tid == 0) __hip_atomic_store(a.cand_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t pre = 0;
+  int nbits = 0;
+  int64_t blw = 0;
+  int64_t mm = n;
+  while (mm > a.cand_cap) {
+    if (nbits >= 64) {
+      if (tid == 0) set_err(a, kErrSelect);
+      return false;
     }
-    const uint64_t s3 = wall_clock64();
+    unsigned int* Hcur = a.hist + (hist_passes % 3) * kHistBins;
+    unsigned int* Hnext = a.hist + ((hist_passes + 1) % 3) * kHistBins;
+    for (int b = tid; b < kHistBins; b += kBlock) hist[b] = 0u;
+    if (g == 0)
+      for (int b = tid; b < kHistBins; b += kBlock) Hnext[b] = 0u;
+    __syncthreads();
+    const int shift = 56 - nbits;
+    for (int64_t p = p0 + tid; p < p1; p += kBlock) {
+      uint64_t k0, k1;
+      sample_key_pair(a.seed, t, static_cast<uint64_t>(p), k0, k1);
+      if (key_in_window(k0, pre, nbits)) atomicAdd(&hist[(k0 >> shift) & 255u], 1u);
+      if (2 * p + 1 < n && key_in_window(k1, pre, nbits))
+        atomicAdd(&hist[(k1 >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int b = tid; b < kHistBins; b += kBlock) {
+      const unsigned int v2 = hist[b];
+      if (v2) atomicAdd(&Hcur[b], v2);
+    }
     if (!sync_grid(a)) return false;
-    if (g == 0 && tid == 0) a.counters[kCntTicksSelect] += static_cast<int64_t>(s3 - s2);
-    if (!hit) {
-      // exact fallback: histogram passes over the key prefixes
-      uint64_t pre = 0;
-      int nbits = 0;
-      int64_t blw = 0;
-      int64_t mm = n;
-      while (mm > a.cand_cap) {
-        if (nbits >= 64) {
-          if (tid == 0) set_err(a, kErrSelect);
-          return false;
-        }
-        unsigned int* Hcur = a.hist + (hist_passes % 3) * kHistBins;
-        unsigned int* Hnext = a.hist + ((hist_passes + 1) % 3) * kHistBins;
-        for (int b = tid; b < kHistBins; b += kBlock) hist[b] = 0u;
-        if (g == 0)
-          for (int b = tid; b < kHistBins; b += kBlock) Hnext[b] = 0u;
-        __syncthreads();
-        const int shift = 56 - nbits;
-        for (int64_t p = p0 + tid; p < p1; p += kBlock) {
-          uint64_t k0, k1;
-          sample_key_pair(a.seed, t, static_cast<uint64_t>(p), k0, k1);
-          if (key_in_window(k0, pre, nbits)) atomicAdd(&hist[(k0 >> shift) & 255u], 1u);
-          if (2 * p + 1 < n && key_in_window(k1, pre, nbits))
-            atomicAdd(&hist[(k1 >> shift) & 255u], 1u);
-        }
-        __syncthreads();
-        for (int b = tid; b < kHistBins; b += kBlock) {
-          const unsigned int v2 = hist[b];
-          if (v2) atomicAdd(&Hcur[b], v2);
-        }
-        if (!sync_grid(a)) return false;
-        const int64_t need = a.s - blw;
-        if (tid == 0) L.misc[1] = -1;
-        const int hb = (tid < kHistBins) ? static_cast<int>(Hcur[tid]) : 0;
-        int tot = 0;
-        const int ex = block_exclusive_scan<kBlock, int>(hb, L.tmpi, tot);
-        if (tid < kHistBins && ex < need && need <= static_cast<int64_t>(ex) + hb) {
-          L.misc[1] = tid;
-          L.misc64[0] = ex;
-          L.misc64[1] = hb;
-        }
-        __syncthreads();
-        if (L.misc[1] < 0) {
-          if (tid == 0) set_err(a, kErrSelect);
-          return false;
-        }
-        blw += L.misc64[0];
-        pre = (pre << 8) | static_cast<uint64_t>(L.misc[1]);
-        nbits += 8;
-        mm = L.misc64[1];
-        ++hist_passes;
-        __syncthreads();
-      }
-      const uint64_t lo = nbits ? pre << (64 - nbits) : 0ull;
-      const uint64_t hi = nbits ? lo | (~0ull >> nbits) : ~0ull;
-      collect_pass(a, pl, L, t, p0, p1, lo, hi);
-      if (!sync_grid(a)) return false;
-      if (g == 0) {
-        const int64_t got = __hip_atomic_load(a.cand_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (got != mm) {
-          if (tid == 0) set_err(a, kErrSelect);
-          return false;
-        }
-        if (!select_threshold(a, pl, L, blw, mm, ppw)) return false;
-        if (tid == 0) __hip_atomic_store(a.cand_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (!sync_grid(a)) return false;
+    const int64_t need = a.s - blw;
+    if (tid == 0) L.misc[1] = -1;
+    const int hb = (tid < kHistBins) ? static_cast<int>(Hcur[tid]) : 0;
+    int tot = 0;
+    const int ex = block_exclusive_scan<kBlock, int>(hb, L.tmpi, tot);
+    if (tid < kHistBins && ex < need && need <= static_cast<int64_t>(ex) + hb) {
+      L.misc[1] = tid;
+      L.misc64[0] = ex;
+      L.misc64[1] = hb;
     }
+    __syncthreads();
+    if (L.misc[1] < 0) {
+      if (tid == 0) set_err(a, kErrSelect);
+      return false;
+    }
+    blw += L.misc64[0];
+    pre = (pre << 8) | static_cast<uint64_t>(L.misc[1]);
+    nbits += 8;
+    mm = L.misc64[1];
+    ++hist_passes;
+    __syncthreads();
   }
+  const uint64_t lo = nbits ? pre << (64 - nbits) : 0ull;
+  const uint64_t hi = nbits ? lo | (~0ull >> nbits) : ~0ull;
+  collect_pass(a, sb, pl, L, t, p0, p1, lo, hi);
+  if (!sync_grid(a)) return false;
+  if (g == 0) {
+    const int64_t got = __hip_atomic_load(sb.cand_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (got != mm) {
+      if (tid == 0) set_err(a, kErrSelect);
+      return false;
+    }
+    if (!select_threshold(a, sb, pl, L, blw, mm, ppw)) return false;
+    if (tid == 0) __hip_atomic_store(sb.cand_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return sync_grid(a);
+}
 
-  // emit in index order and gather: each thread takes a contiguous run of
-  // pairs, counts its selected points from the codes (a key inside the window
-  // is recomputed and compared with the threshold pair), and writes them at
-  // its offset from one block-wide scan
-  const uint64_t tk = a.thr[0];
-  const int64_t ti = static_cast<int64_t>(a.thr[1]);
+// Emit sample slot sb in index order and gather its rows: each thread takes a
+// contiguous run of pairs, counts its selected points from the codes (a key
+// inside the window is recomputed and compared with the threshold pair), and
+// writes them at its offset from one block-wide scan.  No barrier.
+template <int DM>
+__device__ __forceinline__ void emit_sample(const SolverArgs& a, const SBuf& sb, Lds& L, uint32_t t,
+                                            int tt, int64_t p0, int64_t p1) {
+  const int tid = threadIdx.x;
+  const int g = blockIdx.x;
+  const int64_t n = a.n;
+  const uint64_t tk = sb.thr[0];
+  const int64_t ti = static_cast<int64_t>(sb.thr[1]);
   const int64_t per = (p1 - p0 + kBlock - 1) / kBlock;
   const int64_t q0 = p0 + tid * per;
   const int64_t q1 = imin64(p1, q0 + per);
@@ -512,10 +528,9 @@ __device__ __forceinline__ bool sample_phase(const SolverArgs& a, const LdsPlan&
     sample_key_pair(a.seed, t, static_cast<uint64_t>(i >> 1), ke, ko);
     return pair_le((i & 1) ? ko : ke, i, tk, ti);
   };
-  const uint64_t s4 = wall_clock64();
-  const uint16_t* code2 = reinterpret_cast<const uint16_t*>(a.selcode);
+  const uint16_t* code2 = reinterpret_cast<const uint16_t*>(sb.selcode);
   auto codes_of = [&](int64_t p) -> int {  // both codes of pair p (odd n: last pair has one)
-    return (2 * p + 1 < n) ? static_cast<int>(code2[p]) : static_cast<int>(a.selcode[2 * p]);
+    return (2 * p + 1 < n) ? static_cast<int>(code2[p]) : static_cast<int>(sb.selcode[2 * p]);
   };
   // selection bits of this thread's points (up to 128), decided once
   uint64_t bits_lo = 0, bits_hi = 0;
@@ -541,25 +556,84 @@ __device__ __forceinline__ bool sample_phase(const SolverArgs& a, const LdsPlan&
   }
   int total = 0;
   const int excl = block_exclusive_scan<kBlock, int>(mine, L.tmpi, total);
-  int64_t pos = static_cast<int64_t>(a.wg_off[g]) + excl;
+  int64_t pos = static_cast<int64_t>(sb.wg_off[g]) + excl;
   if (fits) {
     while (bits_lo) {
       const int j = __builtin_ctzll(bits_lo);
       bits_lo &= bits_lo - 1;
-      emit_point<DM>(a, tt, pos++, 2 * q0 + j);
+      emit_point<DM>(a, sb, tt, pos++, 2 * q0 + j);
     }
     while (bits_hi) {
       const int j = __builtin_ctzll(bits_hi);
       bits_hi &= bits_hi - 1;
-      emit_point<DM>(a, tt, pos++, 2 * q0 + 64 + j);
+      emit_point<DM>(a, sb, tt, pos++, 2 * q0 + 64 + j);
     }
   } else {
     for (int64_t p = q0; p < q1; ++p) {
       const int c = codes_of(p);
-      if (selected(2 * p, c & 255)) emit_point<DM>(a, tt, pos++, 2 * p);
-      if (2 * p + 1 < n && selected(2 * p + 1, c >> 8)) emit_point<DM>(a, tt, pos++, 2 * p + 1);
+      if (selected(2 * p, c & 255)) emit_point<DM>(a, sb, tt, pos++, 2 * p);
+      if (2 * p + 1 < n && selected(2 * p + 1, c >> 8)) emit_point<DM>(a, sb, tt, pos++, 2 * p + 1);
     }
   }
+}
+
+// Samples tt0 .. tt0 + nb - 1 of this call into slots 0 .. nb - 1: the s
+// smallest (key, index) pairs of each, emitted in index order with their rows
+// gathered.  The key window [win_lo, win_hi] predicted from the order
+// statistics of uniform keys (the s-th smallest of n lies within 8 standard
+// deviations of s/n of the key range, plus a margin) almost always holds the
+// threshold, so one collect pass per sample suffices; a miss takes the exact
+// histogram path for that sample.  One barrier after collecting all samples,
+// the thresholds selected in parallel (workgroup g takes samples g, g + G,
+// ...), one barrier, then every sample emitted and one barrier: three grid
+// barriers per batch.
+template <int DM>
+__device__ __forceinline__ bool sample_batch(const SolverArgs& a, const LdsPlan& pl, Lds& L, float* Pb,
+                                             int32_t* idxb, int tt0, int nb, int64_t& hist_passes) {
+  const int tid = threadIdx.x;
+  const int g = blockIdx.x;
+  const int G = gridDim.x;
+  const int64_t npairs = (a.n + 1) >> 1;
+  const int64_t ppw = (npairs + G - 1) / G;
+  const int64_t p0 = imin64(npairs, static_cast<int64_t>(g) * ppw);
+  const int64_t p1 = imin64(npairs, p0 + ppw);
+
+  const uint64_t s0 = wall_clock64();
+  for (int b = 0; b < nb; ++b)
+    collect_pass(a, slot_bufs(a, Pb, idxb, b), pl, L, static_cast<uint32_t>(a.t0 + tt0 + b), p0, p1,
+                 a.win_lo, a.win_hi);
+  const uint64_t s1 = wall_clock64();
+  if (!sync_grid(a)) return false;
+  const uint64_t s2 = wall_clock64();
+  if (g == 0 && tid == 0) {
+    a.counters[kCntTicksCollect] += static_cast<int64_t>(s1 - s0);
+    a.counters[kCntTicksCollectWait] += static_cast<int64_t>(s2 - s1);
+  }
+  for (int b = g; b < nb; b += G) {
+    const SBuf sb = slot_bufs(a, Pb, idxb, b);
+    const int64_t below = keys_below(sb, L);
+    const int64_t m = __hip_atomic_load(sb.cand_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool hit = m <= a.cand_cap && below < a.s && a.s <= below + m;
+    if (hit && !select_threshold(a, sb, pl, L, below, m, ppw)) return false;
+    if (tid == 0) {
+      a.smiss[b] = hit ? 0 : 1;
+      __hip_atomic_store(sb.cand_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+  }
+  const uint64_t s3 = wall_clock64();
+  if (!sync_grid(a)) return false;
+  if (g == 0 && tid == 0) a.counters[kCntTicksSelect] += static_cast<int64_t>(s3 - s2);
+  for (int b = 0; b < nb; ++b) {
+    if (__hip_atomic_load(&a.smiss[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
+        !exact_select(a, slot_bufs(a, Pb, idxb, b), pl, L, static_cast<uint32_t>(a.t0 + tt0 + b), p0,
+                      p1, ppw, hist_passes))
+      return false;
+  }
+  const uint64_t s4 = wall_clock64();
+  for (int b = 0; b < nb; ++b)
+    emit_sample<DM>(a, slot_bufs(a, Pb, idxb, b), L, static_cast<uint32_t>(a.t0 + tt0 + b), tt0 + b,
+                    p0, p1);
   if (g == 0 && tid == 0) a.counters[kCntTicksEmit] += static_cast<int64_t>(wall_clock64() - s4);
   return sync_grid(a);
 }
@@ -1149,13 +1223,27 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
   }
   if (a.init_incumbent) ok = sync_grid(a);
 
+  // samples are drawn a.sbatch at a time into slots; the phases below read
+  // the current sample's rows through a.P
+  float* const Pb = a.P;
+  int32_t* const idxb = a.idx;
+  bool stored = false;  // the previous sample replaced the incumbent (grid-uniform)
   for (int tt = 0; ok && tt < a.T; ++tt) {
     const uint32_t t = static_cast<uint32_t>(a.t0 + tt);
+    const int slot = tt % a.sbatch;
     uint64_t clk0 = wall_clock64();
-    if (a.do_sample) {
-      ok = sample_phase<DM>(a, pl, L, t, tt, c_hist);
+    if (a.do_sample && slot == 0) {
+      const int nb = a.T - tt < a.sbatch ? a.T - tt : a.sbatch;
+      ok = sample_batch<DM>(a, pl, L, Pb, idxb, tt, nb, c_hist);
+      if (!ok) break;
+    } else if (stored) {
+      // workgroup 0 wrote the incumbent at the end of the previous sample;
+      // every workgroup reads it below, so wait for that write to land
+      ok = sync_grid(a);
       if (!ok) break;
     }
+    if (Pb) a.P = Pb + static_cast<size_t>(slot) * a.s * a.d;
+    a.idx = idxb + static_cast<size_t>(slot) * a.s;
     uint64_t clk1 = wall_clock64();
     c_tsample += clk1 - clk0;
     load_incumbent<DM>(a, L);
@@ -1200,12 +1288,14 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
     }
     c_tlloyd += wall_clock64() - clk1;
     if (a.do_keep) {
-      if (f_ref > f) {
+      stored = f_ref > f;
+      if (stored) {
         if (g == 0) store_incumbent<DM>(a, L, f);
         ++c_replaced;
       }
-    } else if (g == 0) {
-      store_incumbent<DM>(a, L, f);
+    } else {
+      stored = true;
+      if (g == 0) store_incumbent<DM>(a, L, f);
     }
     if (g == 0 && tid == 0 && a.sample_f) a.sample_f[tt] = f;
     ++c_samples;
@@ -1289,8 +1379,9 @@ bm_status solver_max_grid(int dm, size_t lds, int* max_grid) {
 bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t stream) {
   // every buffer a requested phase touches must exist
   const bool rows = a.do_seed || a.do_lloyd || a.do_keep || a.do_gather;
-  if ((rows && !a.P) || (a.do_gather && !a.X) || (a.do_sample && (!a.idx || !a.cand_key || !a.selcode ||
-      !a.cand_idx || !a.wg_lo || !a.wg_off || !a.thr || !a.hist || !a.cand_count)) ||
+  if ((rows && !a.P) || (a.do_gather && !a.X) || a.sbatch < 1 || (!a.do_sample && a.sbatch != 1) ||
+      (a.do_sample && (!a.idx || !a.cand_key || !a.selcode || !a.cand_idx || !a.wg_lo ||
+                       !a.wg_off || !a.thr || !a.hist || !a.cand_count || !a.smiss)) ||
       (rows && (!a.labels || !a.w)) || !a.Cinc || !a.deg_inc || !a.f_opt || !a.c64 || !a.sums ||
       !a.cnt || !a.sse_part || !a.wsum || !a.phi_part || !a.cand || !a.counters || !a.bar ||
       !a.err || !a.sample_f || grid < 1 || grid > kMaxGrid)
@@ -1323,6 +1414,15 @@ namespace bm {
 // deviation sqrt(s (1 - s/n)); the window spans 8 deviations plus 64 ranks on
 // either side, mapped to key values.  The candidate list holds the expected
 // window count with ample slack; a miss falls back to exact histogram passes.
+int sample_slots(int64_t n, int64_t s, int d, int T, int64_t cand_cap) {
+  const double per = 4.0 * static_cast<double>(s) * d + 4.0 * s + static_cast<double>(n) +
+                     12.0 * cand_cap + 8.0 * kMaxGrid + 64.0;
+  double b = floor(kSampleBatchBytes / per);
+  if (b > T) b = T;
+  if (b < 1) b = 1;
+  return static_cast<int>(b);
+}
+
 void sampler_window(int64_t n, int64_t s, uint64_t* lo, uint64_t* hi, int64_t* cap) {
   const double nn = static_cast<double>(n), ss = static_cast<double>(s);
   const double sigma = sqrt(ss * (1.0 - ss / nn));
