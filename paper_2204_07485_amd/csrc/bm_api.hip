@@ -228,7 +228,7 @@ struct SolverBuffers {
 
 // Lay out every solver buffer; with base == nullptr only the size is computed.
 static void layout_solver(char* base, int64_t n, int64_t s, int d, int k, int T, int64_t cand_cap, bool own_P,
-                          bool own_idx, bool own_labels, bool own_inc, int final_grid, int sbatch,
+                          bool own_idx, bool no_labels, bool own_inc, int final_grid, int sbatch,
                           SolverBuffers* b) {
   Layout L;
   L.base = base;
@@ -259,13 +259,12 @@ static void layout_solver(char* base, int64_t n, int64_t s, int d, int k, int T,
   a.sample_f = L.take<double>(T > 0 ? T : 1);
   float* P = L.take<float>(own_P ? B * static_cast<size_t>(s) * d : 1);
   int32_t* idx = L.take<int32_t>(own_idx ? B * static_cast<size_t>(s) : 1);
-  int32_t* lab = L.take<int32_t>(own_labels ? s : 1);
   float* Cinc = L.take<float>(own_inc ? static_cast<size_t>(k) * d : 1);
   uint8_t* deg = L.take<uint8_t>(k);
   double* fopt = L.take<double>(1);
   if (own_P) a.P = P;
   if (own_idx) a.idx = idx;
-  if (own_labels) a.labels = lab;
+  if (no_labels) a.labels = nullptr;  // sample labels are then not written at all
   if (own_inc) a.Cinc = Cinc;
   a.deg_inc = deg;
   a.f_opt = fopt;
@@ -278,16 +277,16 @@ static void layout_solver(char* base, int64_t n, int64_t s, int d, int k, int T,
 
 static bm_status prepare_solver(hipStream_t stream, int64_t n, int64_t s, int d, int k, int T,
                                 int64_t cand_cap,
-                                bool own_P, bool own_idx, bool own_labels, bool own_inc,
+                                bool own_P, bool own_idx, bool no_labels, bool own_inc,
                                 int final_grid, int sbatch, SolverBuffers* b) {
   SolverArgs keep = b->a;
-  layout_solver(nullptr, n, s, d, k, T, cand_cap, own_P, own_idx, own_labels, own_inc, final_grid,
+  layout_solver(nullptr, n, s, d, k, T, cand_cap, own_P, own_idx, no_labels, own_inc, final_grid,
                 sbatch, b);
   bm_status st = BM_OK;
   char* base = static_cast<char*>(scratch_get(b->bytes, stream, &st));
   if (!base) return st;
   b->a = keep;
-  layout_solver(base, n, s, d, k, T, cand_cap, own_P, own_idx, own_labels, own_inc, final_grid,
+  layout_solver(base, n, s, d, k, T, cand_cap, own_P, own_idx, no_labels, own_inc, final_grid,
                 sbatch, b);
   BM_HIP(hipMemsetAsync(base, 0, b->ctrl_bytes, stream));
   if (final_grid > 0) {

@@ -14,20 +14,45 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 
 // ---------------------------------------------------------------------------
 // Grid barrier for a cooperative launch (every workgroup is resident).
-// Arrival counter plus generation word.  Each workgroup publishes its writes
-// with one agent-scope release fence before arriving, polls the generation
-// with relaxed loads (no cache maintenance per poll) and takes one
-// agent-scope acquire fence after the wait; the last arriver acquires all
-// arrivals, resets the counter and publishes the next generation with a
-// release store.  A waiter that polls more than spin_limit times raises `abort`,
-// and every later barrier returns false at once, so a logic error ends the
-// kernel instead of hanging it.
-struct GridBarrier {
-  unsigned int arrive;
-  unsigned int gen;
-  int abort;
-  int pad;
+//
+// Two-level arrival: the G workgroups form about sqrt(G) groups of
+// consecutive workgroups, each with its own arrival counter; the last arriver
+// of a group arrives at the top counter, and the last of those publishes the
+// next generation to one word per group, which that group's members poll.
+// Every word sits in a cache line of its own, so no line takes more than
+// about sqrt(G) of the same-address atomics or pollers: same-address device
+// atomics are serialized where device coherence is kept, which made a single
+// counter cost time linear in G.
+//
+// Ordering: a workgroup publishes its writes with one agent-scope release
+// fence before arriving; a group's last arriver takes an acquire-release
+// fence before forwarding the group to the top counter; the final arriver
+// acquires, resets the top counter and release-stores the generation words;
+// a waiter polls with relaxed loads (no cache maintenance per poll) and takes
+// one agent-scope acquire fence after the wait.  Counters are reset by the
+// arriver that completes them, before the release that lets their group
+// arrive again.  A waiter that polls more than spin_limit times raises
+// `abort`, and every later barrier returns false at once, so a logic error
+// ends the kernel instead of hanging it.
+struct alignas(128) BarrierWord {
+  unsigned int v;
+  unsigned int pad[31];
 };
+constexpr int kBarrierMaxGroups = 64;  // groups of ceil(sqrt(G)) for G <= 4096
+
+struct GridBarrier {
+  BarrierWord top;                        // groups whose members have all arrived
+  BarrierWord abort;                      // nonzero: every barrier fails at once
+  BarrierWord arrive[kBarrierMaxGroups];  // arrivals per group
+  BarrierWord gen[kBarrierMaxGroups];     // generation, one copy per group
+};
+
+__device__ __forceinline__ unsigned int barrier_group_size(unsigned int nblocks) {
+  unsigned int s = static_cast<unsigned int>(__builtin_sqrtf(static_cast<float>(nblocks)));
+  while (s * s < nblocks) ++s;
+  while (s > 1 && (s - 1) * (s - 1) >= nblocks) --s;
+  return s;  // ceil(sqrt(nblocks))
+}
 
 __device__ __forceinline__ bool grid_barrier(GridBarrier* b, unsigned int nblocks,
                                              unsigned int spin_limit) {
@@ -35,29 +60,44 @@ __device__ __forceinline__ bool grid_barrier(GridBarrier* b, unsigned int nblock
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = 1;
-    if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    if (__hip_atomic_load(&b->abort.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
       ok = 0;
     } else {
-      const unsigned int g =
-          __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned int S = barrier_group_size(nblocks);
+      const unsigned int grp = blockIdx.x / S;
+      const unsigned int gsize = (nblocks - grp * S) < S ? (nblocks - grp * S) : S;
+      const unsigned int ngroups = (nblocks + S - 1) / S;
+      unsigned int* my_gen = &b->gen[grp].v;
+      const unsigned int g = __hip_atomic_load(my_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      bool wait = true;
       const unsigned int prev =
-          __hip_atomic_fetch_add(&b->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (prev == nblocks - 1) {
-        // acquire every arrival, reset the counter, then publish the new
-        // generation with a release store (ordered after the reset)
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        __hip_atomic_store(&b->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&b->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
+          __hip_atomic_fetch_add(&b->arrive[grp].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (prev == gsize - 1) {
+        // the group is complete: reset its counter, then forward it
+        __hip_atomic_store(&b->arrive[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        const unsigned int prev2 =
+            __hip_atomic_fetch_add(&b->top.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev2 == ngroups - 1) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          __hip_atomic_store(&b->top.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          for (unsigned int q = 0; q < ngroups; ++q)
+            __hip_atomic_store(&b->gen[q].v, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          wait = false;
+        }
+      }
+      if (wait) {
         unsigned int polls = 0;
-        while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-          if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        while (__hip_atomic_load(my_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+          if ((polls & 15u) == 15u &&
+              __hip_atomic_load(&b->abort.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
             ok = 0;
             break;
           }
           if (++polls > spin_limit) {
-            __hip_atomic_store(&b->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&b->abort.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ok = 0;
             break;
           }

@@ -35,6 +35,8 @@ enum Counter {
   kCntTicksCollectWait = 15,
   kCntTicksSelect = 16,
   kCntTicksEmit = 17,
+  kCntTicksAssign = 18,  // Lloyd pass: assignment + local accumulation / global flush
+  kCntTicksFlush = 19,
 };
 
 enum SolverError {

@@ -20,6 +20,8 @@
 // pairs; per-workgroup partial results are combined after a grid barrier.
 #include <math.h>
 
+#include <type_traits>
+
 #include "bm_internal.h"
 #include "bm_rng.h"
 
@@ -104,9 +106,12 @@ __device__ __forceinline__ Lds carve(unsigned char* base, const LdsPlan& p) {
   return L;
 }
 
+static_assert(kMaxGrid <= kBarrierMaxGroups * kBarrierMaxGroups,
+              "the grid barrier's groups must cover the largest grid");
+
 __device__ __forceinline__ void set_err(const SolverArgs& a, int code) {
   atomicCAS(a.err, 0, code);
-  __hip_atomic_store(&a.bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&a.bar->abort.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ bool sync_grid(const SolverArgs& a) {
@@ -910,14 +915,17 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
 // ---------------------------------------------------------------------------
 // 3. K-means on the sample.
 
-template <int DM>
+// SUMS_LDS: sums_dst is the workgroup's LDS copy (otherwise the global ring);
+// a compile-time choice, so the accumulation compiles to LDS or global
+// atomics instead of generic ones.
+template <int DM, bool SUMS_LDS>
 __device__ __forceinline__ void assign_row(const SolverArgs& a, Lds& L, const float (&x)[DM],
                                            int64_t i, int na, bool accumulate, double* sums_dst,
                                            int ld, int* cnt_l, double& sse) {
   int bj;
   float bd;
   nearest_f32<DM>(x, L.C, L.act, na, bj, bd);
-  a.labels[i] = bj;
+  if (a.labels) a.labels[i] = bj;
   sse += dist2_f64_row<DM>(x, L.C + bj * DM);
   if (accumulate) {
     atomicAdd(&cnt_l[bj], 1);
@@ -947,6 +955,7 @@ __device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& 
   int32_t* cring = a.cnt + (static_cast<size_t>(pass % 3) * kReplicas + rep) * k;
   double* sums_l = reinterpret_cast<double*>(L.B + pl.sums);
   int* cnt_l = reinterpret_cast<int*>(L.B + pl.cntl);
+  const uint64_t a0 = wall_clock64();
 
   if (g == 0) {  // clear the ring slot (all replicas) the next pass accumulates into
     double* nring = a.sums + static_cast<size_t>((pass + 1) % 3) * kReplicas * kd;
@@ -961,22 +970,27 @@ __device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& 
     for (int j = tid; j < k; j += kBlock) cnt_l[j] = 0;
     __syncthreads();
   }
-  double* sums_dst = a.sums_in_lds ? sums_l : ring;
   double sse = 0.0;
-  if (cached) {
+  auto rows = [&](auto sums_lds_tag, double* sums_dst) {
+    constexpr bool kL = decltype(sums_lds_tag)::value;
+    if (cached) {
 #pragma unroll
-    for (int q = 0; q < RowCache<DM>::kRows; ++q) {
-      const int64_t i = r0 + tid + static_cast<int64_t>(q) * kBlock;
-      if (i < r1) assign_row<DM>(a, L, rc.x[q], i, na, accumulate, sums_dst, ld, cnt_l, sse);
+      for (int q = 0; q < RowCache<DM>::kRows; ++q) {
+        const int64_t i = r0 + tid + static_cast<int64_t>(q) * kBlock;
+        if (i < r1) assign_row<DM, kL>(a, L, rc.x[q], i, na, accumulate, sums_dst, ld, cnt_l, sse);
+      }
+    } else {
+      for (int64_t i = r0 + tid; i < r1; i += kBlock) {
+        float x[DM];
+        load_row_f32<DM>(a.P + static_cast<size_t>(i) * d, d, x);
+        assign_row<DM, kL>(a, L, x, i, na, accumulate, sums_dst, ld, cnt_l, sse);
+      }
     }
-  } else {
-    for (int64_t i = r0 + tid; i < r1; i += kBlock) {
-      float x[DM];
-      load_row_f32<DM>(a.P + static_cast<size_t>(i) * d, d, x);
-      assign_row<DM>(a, L, x, i, na, accumulate, sums_dst, ld, cnt_l, sse);
-    }
-  }
+  };
+  if (a.sums_in_lds) rows(std::true_type{}, sums_l);
+  else rows(std::false_type{}, ring);
   const double wsse = block_sum_f64<kBlock>(sse, L.tmpd);
+  const uint64_t f0 = wall_clock64();
   if (accumulate) {
     if (a.sums_in_lds) {
       for (int e = tid; e < kd; e += kBlock) {
@@ -990,7 +1004,11 @@ __device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& 
   if (tid == 0) a.sse_part[(pass & 1u) * kMaxGrid + g] = wsse;
   const uint64_t b0 = wall_clock64();
   const bool ok = sync_grid(a);
-  if (g == 0 && tid == 0) a.counters[kCntTicksBarrier] += static_cast<int64_t>(wall_clock64() - b0);
+  if (g == 0 && tid == 0) {
+    a.counters[kCntTicksAssign] += static_cast<int64_t>(f0 - a0);
+    a.counters[kCntTicksFlush] += static_cast<int64_t>(b0 - f0);
+    a.counters[kCntTicksBarrier] += static_cast<int64_t>(wall_clock64() - b0);
+  }
   return ok;
 }
 
@@ -1041,15 +1059,15 @@ __device__ __forceinline__ double gather_pass(const SolverArgs& a, const LdsPlan
 // computes the same values.  The FP64 means live in LDS when they fit,
 // otherwise in c64[it % 2] (every workgroup writes the same bits; the
 // previous means are read from the other half).
-template <int DM>
+template <int DM, bool C64_LDS>
 __device__ __forceinline__ double update_centroids(const SolverArgs& a, const LdsPlan& pl, Lds& L, uint32_t used,
                                    int it) {
   const int tid = threadIdx.x;
   const int d = a.d;
   const int k = a.k;
   const double* ring = a.sums + static_cast<size_t>(used % 3) * kReplicas * k * d;
-  const double* c_old = a.c64_in_lds ? L.c64 : a.c64 + static_cast<size_t>((it + 1) & 1) * k * d;
-  double* c_new = a.c64_in_lds ? L.c64 : a.c64 + static_cast<size_t>(it & 1) * k * d;
+  const double* c_old = C64_LDS ? L.c64 : a.c64 + static_cast<size_t>((it + 1) & 1) * k * d;
+  double* c_new = C64_LDS ? L.c64 : a.c64 + static_cast<size_t>(it & 1) * k * d;
   const int* cnt_l = reinterpret_cast<const int*>(L.B + pl.cntl);
   // staged sums, overwritten in place by the squared coordinate moves
   double* dsq = a.sums_in_lds ? reinterpret_cast<double*>(L.B + pl.sums) : nullptr;
@@ -1131,10 +1149,11 @@ __device__ __forceinline__ bool lloyd_phase(const SolverArgs& a, const LdsPlan& 
   bool by_objective = false;
   const int d = a.d;
   // FP64 means start as the FP32 start centroids
-  double* c0 = a.c64_in_lds ? L.c64 : a.c64;
   for (int e = threadIdx.x; e < a.k * d; e += kBlock) {
     const int j = e / d;
-    c0[e] = static_cast<double>(L.C[j * DM + (e - j * d)]);
+    const double v = static_cast<double>(L.C[j * DM + (e - j * d)]);
+    if (a.c64_in_lds) L.c64[e] = v;
+    else a.c64[e] = v;
   }
   for (int it = 1; it <= a.max_iter; ++it) {
     const int na = L.misc[0];
@@ -1149,7 +1168,8 @@ __device__ __forceinline__ bool lloyd_phase(const SolverArgs& a, const LdsPlan& 
       by_objective = true;
       break;
     }
-    const double shift = update_centroids<DM>(a, pl, L, used, it);
+    const double shift = a.c64_in_lds ? update_centroids<DM, true>(a, pl, L, used, it)
+                                      : update_centroids<DM, false>(a, pl, L, used, it);
     const uint64_t c2t = wall_clock64();
     tk_pass += c1t - c0t;
     tk_post += c2t - c1t;
@@ -1382,7 +1402,7 @@ bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t s
   if ((rows && !a.P) || (a.do_gather && !a.X) || a.sbatch < 1 || (!a.do_sample && a.sbatch != 1) ||
       (a.do_sample && (!a.idx || !a.cand_key || !a.selcode || !a.cand_idx || !a.wg_lo ||
                        !a.wg_off || !a.thr || !a.hist || !a.cand_count || !a.smiss)) ||
-      (rows && (!a.labels || !a.w)) || !a.Cinc || !a.deg_inc || !a.f_opt || !a.c64 || !a.sums ||
+      (rows && !a.w) || !a.Cinc || !a.deg_inc || !a.f_opt || !a.c64 || !a.sums ||
       !a.cnt || !a.sse_part || !a.wsum || !a.phi_part || !a.cand || !a.counters || !a.bar ||
       !a.err || !a.sample_f || grid < 1 || grid > kMaxGrid)
     return set_error(BM_EINVAL, "solver launch with a missing buffer or bad grid %d", grid);
