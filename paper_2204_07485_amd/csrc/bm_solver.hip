@@ -924,7 +924,17 @@ __device__ __forceinline__ void assign_row(const SolverArgs& a, Lds& L, const fl
                                            int ld, int* cnt_l, double& sse) {
   int bj;
   float bd;
-  nearest_f32<DM>(x, L.C, L.act, na, bj, bd);
+  // every slot in index order: a degenerate slot holds NaN and never compares
+  // smaller, and the strict comparison keeps the lowest index on exact ties
+  bj = L.act[0];
+  bd = __builtin_inff();
+  for (int j = 0; j < a.k; ++j) {
+    const float v = dist2_f32<DM>(x, L.C + j * DM);
+    if (v < bd) {
+      bd = v;
+      bj = j;
+    }
+  }
   if (a.labels) a.labels[i] = bj;
   sse += dist2_f64_row<DM>(x, L.C + bj * DM);
   if (accumulate) {
@@ -1191,6 +1201,8 @@ __device__ __forceinline__ bool lloyd_phase(const SolverArgs& a, const LdsPlan& 
 
 // ---------------------------------------------------------------------------
 
+// The incumbent into LDS; a degenerate slot is filled with NaN so that no
+// distance to it compares smaller in the assignment scans.
 template <int DM>
 __device__ __forceinline__ void load_incumbent(const SolverArgs& a, Lds& L) {
   const int d = a.d;
@@ -1198,7 +1210,7 @@ __device__ __forceinline__ void load_incumbent(const SolverArgs& a, Lds& L) {
   for (int e = threadIdx.x; e < k * DM; e += kBlock) {
     const int j = e / DM;
     const int tdim = e - j * DM;
-    L.C[e] = (tdim < d) ? a.Cinc[j * d + tdim] : 0.f;
+    L.C[e] = (tdim < d) ? (a.deg_inc[j] ? __builtin_nanf("") : a.Cinc[j * d + tdim]) : 0.f;
   }
   for (int j = threadIdx.x; j < k; j += kBlock) L.degf[j] = a.deg_inc[j] ? 1 : 0;
   rebuild_active(L, k);

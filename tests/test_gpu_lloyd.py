@@ -138,3 +138,27 @@ def test_empty_cluster_becomes_degenerate():
     assert gdeg.tolist() == [0, 0, 1]
     assert np.isnan(gC[2]).all()
     assert set(glab.tolist()) == {0, 1}
+
+
+@pytest.mark.parametrize("d", [1, 4, 16])
+def test_exact_ties_keep_lowest_index_on_later_passes(d):
+    # Centroids at x=0 and x=4 that the data keep in place: points at 0 and 4,
+    # mirrored pairs at -2 and 2 (2 is an exact tie between the two
+    # centroids).  Integer coordinates make every FP32 distance exact, so
+    # after the first pass every later pass meets the same exact ties: they
+    # must go to the lower slot (Sec. 2 assignment, lowest index on ties),
+    # also on the passes that reuse the previous pass's distance bounds.
+    s_each = 300
+    rows = ([[0.0]] * s_each + [[4.0]] * s_each + [[-2.0]] * s_each + [[2.0]] * s_each)
+    P = np.zeros((len(rows), d), np.float32)
+    P[:, 0] = np.array(rows, np.float32)[:, 0]
+    C0 = np.zeros((2, d), np.float32)
+    C0[1, 0] = 4.0
+    for max_iter in (1, 2, 5):
+        gC, gdeg, glab, gf, gp = _gpu_lloyd(P, C0, np.zeros(2, np.uint8), max_iter=max_iter, tol=0.0)
+        assert np.array_equal(gC, C0)
+        ties = P[:, 0] == 2.0
+        assert (glab[ties] == 0).all()
+        assert (glab[P[:, 0] == 4.0] == 1).all() and (glab[P[:, 0] <= 0.0] == 0).all()
+        rlab = oracle.assign(P, gC, gdeg)[0]
+        assert np.array_equal(glab, rlab)
