@@ -266,12 +266,23 @@ typedef struct bm_ctx bm_ctx;
 enum { BM_JOB_QUEUED = 0, BM_JOB_RUNNING = 1, BM_JOB_DONE = 2, BM_JOB_FAILED = 3,
        BM_JOB_CANCELLED = 4 };
 
+enum { BM_SERVE_FITS = 0, BM_SERVE_ROUNDS = 1 };
+
 typedef struct bm_serve_config {
   uint32_t struct_size;   /* sizeof(bm_serve_config)                              */
   int32_t slots;          /* concurrent jobs, 1..64 (default 4)                   */
   int64_t hbm_budget;     /* device scratch the context may hold, bytes (8 GiB)   */
   int32_t device;         /* HIP device; -1 = the caller's current device         */
   int32_t grid_per_job;   /* cap of a job's cooperative grid; 0 = CUs / slots     */
+                          /* (BM_SERVE_FITS only)                                 */
+  int32_t mode;           /* BM_SERVE_FITS (default): each slot runs whole fits   */
+                          /* with the persistent solver.  BM_SERVE_ROUNDS: one    */
+                          /* engine keeps up to `slots` jobs in flight, draws and */
+                          /* seeds each job's samples, and runs the Lloyd rounds  */
+                          /* of all of them together in the batched kernels;      */
+                          /* jobs join and leave at round boundaries              */
+  int32_t round_max_k;    /* BM_SERVE_ROUNDS: largest k of a job (default 64)     */
+  int64_t round_max_s;    /* BM_SERVE_ROUNDS: largest sample size (default 50000) */
 } bm_serve_config;
 
 /* One job: the arguments of bigmeans_fit.  opt.stream is ignored (the slot's
@@ -314,7 +325,11 @@ bm_status bm_serve_default_config(bm_serve_config* cfg);
 /* Create a context (cfg NULL = defaults); its worker threads start at once. */
 bm_status bm_ctx_create(const bm_serve_config* cfg, bm_ctx** ctx);
 /* Queue a job (validated as bigmeans_fit validates it; BM_ENOMEM when it needs
- * more scratch than the whole budget).  Returns at once with its id. */
+ * more scratch than the whole budget).  Returns at once with its id.  In
+ * BM_SERVE_ROUNDS mode a job also needs compare_rule BM_CMP_FOPT, s <=
+ * round_max_s and k <= round_max_k (else BM_ENOTSUP); its result agrees with
+ * bigmeans_fit's to rounding (the batched kernels sum in another order), and
+ * its stats carry samples, replacements, lloyd_iters, reseeded and f_opt. */
 bm_status bm_ctx_submit(bm_ctx* ctx, const bm_job* job, int64_t* job_id);
 /* State of a job (info->struct_size must be set). */
 bm_status bm_ctx_poll(bm_ctx* ctx, int64_t job_id, bm_job_info* info);

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libbigmeans.so")
 BM_OK, BM_EINVAL, BM_ENOMEM, BM_EDEVICE, BM_ENOTSUP, BM_ECANCELLED = 0, -1, -2, -3, -4, -5
 BM_ETIMEDOUT = -6
 BM_JOB_QUEUED, BM_JOB_RUNNING, BM_JOB_DONE, BM_JOB_FAILED, BM_JOB_CANCELLED = 0, 1, 2, 3, 4
+BM_SERVE_FITS, BM_SERVE_ROUNDS = 0, 1
 BM_F32, BM_BF16 = 0, 1
 BM_STOP_SHIFT, BM_STOP_REL_OBJ = 0, 1
 BM_CMP_FOPT, BM_CMP_RESAMPLE = 0, 1
@@ -63,7 +64,8 @@ class Stats(ct.Structure):
 
 class ServeConfig(ct.Structure):
     _fields_ = [("struct_size", ct.c_uint32), ("slots", ct.c_int32), ("hbm_budget", ct.c_int64),
-                ("device", ct.c_int32), ("grid_per_job", ct.c_int32)]
+                ("device", ct.c_int32), ("grid_per_job", ct.c_int32), ("mode", ct.c_int32),
+                ("round_max_k", ct.c_int32), ("round_max_s", ct.c_int64)]
 
 
 class Job(ct.Structure):
@@ -358,16 +360,23 @@ def prepare_batch(X, solves, n_local_trials=3, **opts):
 
 
 class Server:
-    """A serving context (bm_ctx): jobs run concurrently on `slots` workers,
-    admitted in order by device-scratch footprint within hbm_budget."""
+    """A serving context (bm_ctx).  mode BM_SERVE_FITS: jobs run whole fits
+    concurrently on `slots` workers, admitted in order by device-scratch
+    footprint within hbm_budget.  mode BM_SERVE_ROUNDS: one engine keeps up to
+    `slots` jobs in flight and runs their Lloyd rounds together in the batched
+    kernels (jobs with s <= round_max_s and k <= round_max_k)."""
 
-    def __init__(self, slots=4, hbm_budget=8 << 30, grid_per_job=0):
+    def __init__(self, slots=4, hbm_budget=8 << 30, grid_per_job=0, mode=0, round_max_k=64,
+                 round_max_s=50_000):
         L = load()
         cfg = ServeConfig()
         _check(L.bm_serve_default_config(ct.byref(cfg)))
         cfg.slots = slots
         cfg.hbm_budget = hbm_budget
         cfg.grid_per_job = grid_per_job
+        cfg.mode = mode
+        cfg.round_max_k = round_max_k
+        cfg.round_max_s = round_max_s
         h = ct.c_void_p()
         _check(L.bm_ctx_create(ct.byref(cfg), ct.byref(h)))
         self._h = h

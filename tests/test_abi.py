@@ -144,11 +144,18 @@ def test_serving_rejects_invalid_arguments(bm):
     cfg = bm.ServeConfig()
     assert lib.bm_serve_default_config(ct.byref(cfg)) == 0
     assert cfg.slots == 4 and cfg.struct_size == ct.sizeof(bm.ServeConfig)
+    assert cfg.mode == bm.BM_SERVE_FITS and cfg.round_max_k == 64 and cfg.round_max_s == 50_000
     h = ct.c_void_p()
     for field, value in (("slots", 0), ("slots", 65), ("hbm_budget", 1000), ("grid_per_job", -1),
-                         ("struct_size", 2)):
+                         ("struct_size", 2), ("mode", 2), ("mode", -1)):
         c2 = bm.ServeConfig()
         lib.bm_serve_default_config(ct.byref(c2))
+        setattr(c2, field, value)
+        assert lib.bm_ctx_create(ct.byref(c2), ct.byref(h)) == bm.BM_EINVAL, field
+    for field, value in (("round_max_k", 0), ("round_max_s", 0), ("round_max_s", 1 << 31)):
+        c2 = bm.ServeConfig()
+        lib.bm_serve_default_config(ct.byref(c2))
+        c2.mode = bm.BM_SERVE_ROUNDS
         setattr(c2, field, value)
         assert lib.bm_ctx_create(ct.byref(c2), ct.byref(h)) == bm.BM_EINVAL, field
     assert lib.bm_ctx_create(ct.byref(cfg), None) == bm.BM_EINVAL

@@ -108,3 +108,72 @@ def test_failed_job_is_reported_and_serving_continues():
         for i in good:
             assert srv.result(i)["sse"] > 0
         assert srv.info()["failed"] == 1
+
+
+def test_rounds_mode_matches_whole_fits():
+    # continuous batching (BM_SERVE_ROUNDS): the jobs' Lloyd rounds share
+    # batched launches; every job must still give what bigmeans_fit gives it
+    # alone (same samples and reseeds; objectives to rounding, since the
+    # batched kernels sum in another order)
+    from paper_2204_07485_amd import bigmeans
+    jobs = _jobs(12, seed=8)
+    with bigmeans.Server(slots=6, mode=bigmeans.BM_SERVE_ROUNDS) as srv:
+        ids = [srv.submit(X, j["k"], j["s"], j["n_samples"], j["seed"], **KW) for j, X in jobs]
+        res = [srv.result(i) for i in ids]
+        info = srv.info()
+    assert info["completed"] == len(jobs) and info["failed"] == 0
+    overlap = 0
+    for a in range(len(res)):
+        for b in range(a + 1, len(res)):
+            if res[a]["t_start_ms"] < res[b]["t_end_ms"] and res[b]["t_start_ms"] < res[a]["t_end_ms"]:
+                overlap += 1
+    assert overlap > 0, "no two jobs were in flight together"
+    for (j, X), r in zip(jobs, res):
+        print(f"job {j['id']}: n={j['n']} d={j['d']} k={j['k']} s={j['s']}", flush=True)
+        alone = bigmeans.bigmeans_fit(X, j["k"], j["s"], j["n_samples"], j["seed"], **KW)
+        assert np.array_equal(r["degenerate"], alone["degenerate"])
+        np.testing.assert_allclose(r["sample_f"], alone["sample_f"], rtol=1e-6)
+        assert_sse(r["sse"], alone["sse"])
+        assert r["stats"]["samples"] == alone["stats"]["samples"] == j["n_samples"]
+        assert r["stats"]["replacements"] == alone["stats"]["replacements"]
+        assert abs(r["stats"]["lloyd_iters"] - alone["stats"]["lloyd_iters"]) <= \
+            0.02 * alone["stats"]["lloyd_iters"] + 2
+        assert r["stats"]["reseeded"] == alone["stats"]["reseeded"]
+        np.testing.assert_allclose(r["centroids"].cpu().numpy(), alone["centroids"].cpu().numpy(),
+                                   rtol=1e-5, atol=1e-5)
+
+
+def test_rounds_mode_bf16_input_and_labels():
+    from paper_2204_07485_amd import bigmeans
+    X32, _ = synth.gaussian_mixture(60_000, 32, 12, seed=31, sigma_range=(0.5, 2.0))
+    X = torch.from_numpy(X32).cuda().to(torch.bfloat16)
+    specs = ((12, 8_000, 6, 77), (7, 5_000, 4, 78))
+    with bigmeans.Server(slots=2, mode=bigmeans.BM_SERVE_ROUNDS) as srv:
+        ids = [srv.submit(X, k, s, T, seed, want_labels=True, **KW) for k, s, T, seed in specs]
+        res = [srv.result(i) for i in ids]
+    for r, (k, s, T, seed) in zip(res, specs):
+        alone = bigmeans.bigmeans_fit(X, k, s, T, seed, **KW)
+        assert_sse(r["sse"], alone["sse"])
+        assert np.array_equal(r["degenerate"], alone["degenerate"])
+        same = (r["labels"].cpu().numpy() == alone["labels"].cpu().numpy()).mean()
+        assert same > 0.9999
+
+
+def test_rounds_mode_rejects_what_it_cannot_batch():
+    from paper_2204_07485_amd import bigmeans
+    (j, X), = _jobs(1, seed=9)
+    with bigmeans.Server(slots=2, mode=bigmeans.BM_SERVE_ROUNDS, round_max_k=8,
+                         round_max_s=4_000) as srv:
+        with pytest.raises(bigmeans.BigmeansError) as e:
+            srv.submit(X, 9, 2_000, 3, 1, **KW)
+        assert e.value.code == bigmeans.BM_ENOTSUP
+        with pytest.raises(bigmeans.BigmeansError) as e:
+            srv.submit(X, 4, 5_000, 3, 1, **KW)
+        assert e.value.code == bigmeans.BM_ENOTSUP
+        with pytest.raises(bigmeans.BigmeansError) as e:
+            srv.submit(X, 4, 2_000, 3, 1, **dict(KW, compare_rule=bigmeans.BM_CMP_RESAMPLE))
+        assert e.value.code == bigmeans.BM_ENOTSUP
+        jid = srv.submit(X, 4, 2_000, 3, 1, **KW)
+        r = srv.result(jid)
+        alone = bigmeans.bigmeans_fit(X, 4, 2_000, 3, 1, **KW)
+        assert_sse(r["sse"], alone["sse"])
