@@ -228,17 +228,16 @@ def serve_stream(n_jobs=200, slots=4, rate=200.0, seed=5):
         data.append(X.contiguous())
     torch.cuda.synchronize()
     kw = dict(max_iter=300, tol=1e-4, stop_rule=bigmeans.BM_STOP_REL_OBJ, n_local_trials=3)
-    out = {}
-    for nslots in sorted({1, 2, slots}):
-        with bigmeans.Server(slots=nslots) as srv:
+
+    def run(mode, nslots, burst):
+        with bigmeans.Server(slots=nslots, mode=mode) as srv:
             for j, X in list(zip(jobs, data))[:4]:  # warm-up
                 srv.result(srv.submit(X, j["k"], j["s"], j["n_samples"], j["seed"], **kw))
-            t_ref = None
             ids = []
             t0 = time.perf_counter()
             for j, X in zip(jobs, data):
                 delay = t0 + j["arrival"] - time.perf_counter()
-                if delay > 0:
+                if delay > 0 and not burst:
                     time.sleep(delay)
                 ids.append(srv.submit(X, j["k"], j["s"], j["n_samples"], j["seed"], **kw))
             res = [srv.result(i) for i in ids]
@@ -247,13 +246,22 @@ def serve_stream(n_jobs=200, slots=4, rate=200.0, seed=5):
         end = np.array([r["t_end_ms"] for r in res])
         lat = end - sub
         span_s = (end.max() - sub.min()) / 1e3
-        out[f"slots_{nslots}"] = {
+        return {
             "jobs": len(res), "jobs_per_s": len(res) / span_s,
             "latency_ms_p50": float(np.percentile(lat, 50)),
             "latency_ms_p99": float(np.percentile(lat, 99)),
             "service_ms_mean": float(np.mean(end - np.array([r["t_start_ms"] for r in res]))),
-            "peak_scratch_mb": info["peak_reserved_bytes"] / 1e6, "grid_per_job": info["grid_per_job"],
-            "failed": info["failed"]}
+            "peak_scratch_mb": info["peak_reserved_bytes"] / 1e6, "failed": info["failed"]}
+
+    out = {}
+    # whole fits per slot (persistent solver) and continuous batching of the
+    # jobs' Lloyd rounds; Poisson arrivals, then all jobs at once (capacity)
+    for nslots in sorted({1, 2, slots}):
+        out[f"fits_slots_{nslots}"] = run(bigmeans.BM_SERVE_FITS, nslots, False)
+    for nslots in (8, 16):
+        out[f"rounds_slots_{nslots}"] = run(bigmeans.BM_SERVE_ROUNDS, nslots, False)
+    out["burst_fits_slots_1"] = run(bigmeans.BM_SERVE_FITS, 1, True)
+    out["burst_rounds_slots_16"] = run(bigmeans.BM_SERVE_ROUNDS, 16, True)
     out["workload"] = (f"serving: {n_jobs} jobs, Poisson arrivals at {rate:g}/s, n log-uniform in "
                        "[1e4, 1e6], d in {2,8,16,32,68,128}, k in [2,50], s = min(n, 50,000), "
                        "20 samples, seed 5")

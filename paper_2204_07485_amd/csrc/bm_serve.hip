@@ -542,6 +542,7 @@ void bm_ctx::engine() {
       r->slot = q;
       j->slot = q;
       A->owner[q] = static_cast<int>(id & 0x7fffffff);
+      A->tiles_dirty = true;  // the work list must cover the new owner's rows
       r->deg_inc.assign(J.k, 1);
       r->f_opt = __builtin_inf();
       live.push_back(std::move(r));

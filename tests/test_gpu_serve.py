@@ -4,6 +4,8 @@ per-sample objectives, degenerate flags and final objective, to the parity
 tolerance), admission keeps the scratch held within the budget, and
 cancellation, timeouts and failures are reported per job while the context
 keeps serving."""
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -176,4 +178,24 @@ def test_rounds_mode_rejects_what_it_cannot_batch():
         jid = srv.submit(X, 4, 2_000, 3, 1, **KW)
         r = srv.result(jid)
         alone = bigmeans.bigmeans_fit(X, 4, 2_000, 3, 1, **KW)
+        assert_sse(r["sse"], alone["sse"])
+
+
+def test_rounds_mode_reuses_slots_across_ticks():
+    # more jobs than slots, equal sample sizes, arriving one by one: a freed
+    # slot is taken by a later job after other rounds have run without it
+    from paper_2204_07485_amd import bigmeans
+    X, _ = synth.gaussian_mixture(40_000, 8, 6, seed=41, sigma_range=(0.5, 2.0))
+    X = torch.from_numpy(X).cuda()
+    specs = [(6, 4_000, 3 + (i % 3), 100 + i) for i in range(9)]
+    with bigmeans.Server(slots=2, mode=bigmeans.BM_SERVE_ROUNDS) as srv:
+        ids = []
+        for k, s, T, seed in specs:
+            ids.append(srv.submit(X, k, s, T, seed, **KW))
+            time.sleep(0.003)
+        res = [srv.result(i) for i in ids]
+    for r, (k, s, T, seed) in zip(res, specs):
+        alone = bigmeans.bigmeans_fit(X, k, s, T, seed, **KW)
+        assert np.array_equal(r["degenerate"], alone["degenerate"])
+        np.testing.assert_allclose(r["sample_f"], alone["sample_f"], rtol=1e-6)
         assert_sse(r["sse"], alone["sse"])
