@@ -28,14 +28,18 @@ FP32_DD_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 2 / 1e12
 COUNTERS = os.path.join(ROOT, "profiles", "solver_medium_hbm_counters.md")
 
 
+# the sources that define the profiled kernels (the persistent solver and the
+# FP32 final pass) and how they are launched
+PROFILED_SOURCES = ("bm_api.hip", "bm_solver.hip", "bm_assign.hip", "bm_device.h", "bm_internal.h",
+                    "bm_rng.h")
+
+
 def source_hash():
-    """Hash of the kernel sources and the C header, to tell whether stored
+    """Hash of the sources of the profiled kernels, to tell whether stored
     profiler byte counts still describe the kernels being timed."""
-    import glob
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2204_07485_amd", "csrc", "*")))
-    files.append(os.path.join(ROOT, "include", "bigmeans.h"))
+    files = [os.path.join(ROOT, "paper_2204_07485_amd", "csrc", f) for f in PROFILED_SOURCES]
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
