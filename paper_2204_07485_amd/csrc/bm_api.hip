@@ -256,6 +256,7 @@ static void layout_solver(char* base, int64_t n, int64_t s, int d, int k, int T,
   a.cand_idx = L.take<int32_t>(B * static_cast<size_t>(cand_cap));
   a.selcode = L.take<uint8_t>(B * ((static_cast<size_t>(n) + 15) & ~size_t(15)));  // 16-byte slots
   a.w = L.take<double>(s);
+  a.dcache = L.take<double>(static_cast<size_t>(kMaxTrials) * s);
   a.sample_f = L.take<double>(T > 0 ? T : 1);
   float* P = L.take<float>(own_P ? B * static_cast<size_t>(s) * d : 1);
   int32_t* idx = L.take<int32_t>(own_idx ? B * static_cast<size_t>(s) : 1);

@@ -80,6 +80,8 @@ struct SolverArgs {
   int32_t* idx;              // sbatch x s
   int32_t* labels;           // s
   double* w;                 // s (K-means++ D^2 weights)
+  double* dcache;            // kMaxTrials x s: FP64 distances of streamed rows to the
+                             // K-means++ candidates of the current centre
   // incumbent
   float* Cinc;               // k x d
   uint8_t* deg_inc;          // k

@@ -720,6 +720,7 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
     if (!L.degf[j]) continue;
     const int na = L.misc[0];
     int64_t pick = -1;
+    int picked = -1;  // which candidate won, when the potentials were computed
     if (na == 0) {
       pick = static_cast<int64_t>(below_from_word(seed_draw(a.seed, t, q), static_cast<uint64_t>(s)));
       ++q;
@@ -855,6 +856,8 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
             if (l < trials) {
               const double dd = dist2_f64_row<DM>(x, cand_rows + l * DM);
               ph[l] += dd < wi ? dd : wi;
+              // streamed rows keep the distance for the D^2 update below
+              if (!cached) a.dcache[static_cast<size_t>(l) * s + i] = dd;
             }
           }
         }
@@ -877,6 +880,7 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
 #pragma unroll
         for (int l = 1; l < kMaxTrials; ++l)
           if (l == best) pick = cands[l];
+        picked = best;
       }
     }
     if (pick < 0 || pick >= s) {  // no valid candidate: stop (error already raised)
@@ -891,12 +895,21 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
     // update D^2 over this workgroup's rows
     double part = 0.0;
     const float* cj = L.C + j * DM;
+    // a streamed row's distance to the winning candidate was kept by the
+    // potentials pass: the same FP64 arithmetic on the same FP32 values (the
+    // candidate is the row P[pick]), so it is read instead of recomputed
+    const bool reuse = !cached && picked >= 0;
     for (int64_t tile = 0; tile < tiles; ++tile) {
       const int64_t i = r0 + tile * kBlock + tid;
       if (i >= r1) continue;
-      float x[DM];
-      row(tile, x);
-      const double dd = dist2_f64_row<DM>(x, cj);
+      double dd;
+      if (reuse) {
+        dd = a.dcache[static_cast<size_t>(picked) * s + i];
+      } else {
+        float x[DM];
+        row(tile, x);
+        dd = dist2_f64_row<DM>(x, cj);
+      }
       const double wold = get_w(tile, i);
       const double wi = (na == 0) ? dd : (dd < wold ? dd : wold);
       set_w(i, wi);
@@ -1414,7 +1427,7 @@ bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t s
   if ((rows && !a.P) || (a.do_gather && !a.X) || a.sbatch < 1 || (!a.do_sample && a.sbatch != 1) ||
       (a.do_sample && (!a.idx || !a.cand_key || !a.selcode || !a.cand_idx || !a.wg_lo ||
                        !a.wg_off || !a.thr || !a.hist || !a.cand_count || !a.smiss)) ||
-      (rows && !a.w) || !a.Cinc || !a.deg_inc || !a.f_opt || !a.c64 || !a.sums ||
+      (rows && (!a.w || !a.dcache)) || !a.Cinc || !a.deg_inc || !a.f_opt || !a.c64 || !a.sums ||
       !a.cnt || !a.sse_part || !a.wsum || !a.phi_part || !a.cand || !a.counters || !a.bar ||
       !a.err || !a.sample_f || grid < 1 || grid > kMaxGrid)
     return set_error(BM_EINVAL, "solver launch with a missing buffer or bad grid %d", grid);
