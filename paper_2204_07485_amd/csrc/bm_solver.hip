@@ -661,6 +661,51 @@ struct RowCache {
 // gives.  The running sum that inverts a draw is taken over workgroup chunks
 // (a fixed-order scan of per-workgroup sums) and then inside the owning chunk.
 
+// FP64 squared distances of the sample row at p to `trials` candidate rows
+// (LDS, DM wide, zero padded), each accumulated with FMAs in dimension order
+// as dist2_f64_row does on a loaded row, so the values are the same; the row
+// is read 16 coordinates at a time instead of being held in registers.
+template <int DM>
+__device__ __forceinline__ void dist2_f64_candidates(const float* __restrict__ p, int d,
+                                                     const float* __restrict__ cand, int trials,
+                                                     double (&out)[kMaxTrials]) {
+#pragma unroll
+  for (int l = 0; l < kMaxTrials; ++l) out[l] = 0.0;
+#pragma unroll
+  for (int t0 = 0; t0 < DM; t0 += 16) {
+    float xc[16];
+    if ((d & 3) == 0) {
+#pragma unroll
+      for (int u = 0; u < 16; u += 4) {
+        if (t0 + u < d) {
+          const float4 v = *reinterpret_cast<const float4*>(p + t0 + u);
+          xc[u] = v.x;
+          xc[u + 1] = v.y;
+          xc[u + 2] = v.z;
+          xc[u + 3] = v.w;
+        } else {
+          xc[u] = xc[u + 1] = xc[u + 2] = xc[u + 3] = 0.f;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) xc[u] = (t0 + u < d) ? p[t0 + u] : 0.f;
+    }
+#pragma unroll
+    for (int l = 0; l < kMaxTrials; ++l) {
+      if (l < trials) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          if (t0 + u < DM) {  // DM need not be a multiple of 16 (e.g. 72)
+            const double e = static_cast<double>(xc[u]) - static_cast<double>(cand[l * DM + t0 + u]);
+            out[l] = __builtin_fma(e, e, out[l]);
+          }
+        }
+      }
+    }
+  }
+}
+
 template <int DM>
 __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32_t t, int64_t r0, int64_t r1,
                              bool cached, const RowCache<DM>& rc, int64_t& nd, int64_t& nres) {
@@ -848,16 +893,23 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
         for (int64_t tile = 0; tile < tiles; ++tile) {
           const int64_t i = r0 + tile * kBlock + tid;
           if (i >= r1) continue;
-          float x[DM];
-          row(tile, x);
+          double dd[kMaxTrials];
+          if (cached || DM < 64) {
+            float x[DM];
+            row(tile, x);
+#pragma unroll
+            for (int l = 0; l < kMaxTrials; ++l)
+              dd[l] = (l < trials) ? dist2_f64_row<DM>(x, cand_rows + l * DM) : 0.0;
+          } else {  // wide rows: stream them rather than hold them
+            dist2_f64_candidates<DM>(a.P + static_cast<size_t>(i) * d, d, cand_rows, trials, dd);
+          }
           const double wi = get_w(tile, i);
 #pragma unroll
           for (int l = 0; l < kMaxTrials; ++l) {
             if (l < trials) {
-              const double dd = dist2_f64_row<DM>(x, cand_rows + l * DM);
-              ph[l] += dd < wi ? dd : wi;
+              ph[l] += dd[l] < wi ? dd[l] : wi;
               // streamed rows keep the distance for the D^2 update below
-              if (!cached) a.dcache[static_cast<size_t>(l) * s + i] = dd;
+              if (!cached) a.dcache[static_cast<size_t>(l) * s + i] = dd[l];
             }
           }
         }
