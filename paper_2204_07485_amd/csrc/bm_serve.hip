@@ -16,16 +16,17 @@
 // identical, objectives agree to rounding), so a job run in the mix gives the
 // result it gives alone.
 //
-// BM_SERVE_ROUNDS mode (continuous batching): one engine thread keeps up to
-// `slots` jobs in flight and advances all of them a step per tick.  A job
-// that needs a sample gets it drawn (Philox keys, Sec. 3.2), gathered, padded
-// into its slot of an arena, and its degenerate incumbent slots reseeded by
-// K-means++ (Sec. 3.3), exactly as the persistent solver does for sample t;
-// then the Lloyd rounds of every job in flight run together, one batched
-// assignment + update launch per (d, stop rule) class and tick, and jobs join
+// BM_SERVE_ROUNDS mode (continuous batching): an engine keeps up to `slots`
+// jobs in flight.  A prep thread gives a job that needs a sample its draw
+// (Philox keys, Sec. 3.2), gathers and pads it into the job's slot of an
+// arena, and reseeds the degenerate incumbent slots by K-means++ (Sec. 3.3),
+// exactly as the persistent solver does for sample t.  The round thread runs
+// the Lloyd rounds of every job whose sample is ready together, one batched
+// assignment + update launch per (d, stop rule) class and round, so jobs join
 // and leave at round boundaries.  A job whose sample converged keeps the
-// better of its incumbent and the new centroids (Alg. 1), moves to its next
-// sample, and after the last one gets the full-data assignment.
+// better of its incumbent and the new centroids (Alg. 1), goes back to the
+// prep thread for its next sample, and after the last one gets the
+// full-data assignment there.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -106,12 +107,18 @@ struct Arena {
   int in_lloyd = 0;                 // slots whose solve is running
 };
 
+// Stage of a job in flight.  The prep thread owns a job in kPrepping and
+// kFinalizing, the round thread in kLloyd; transitions happen under the
+// context's mutex, after the owner has synchronized its stream.
+enum Stage { kPrep, kPrepping, kReady, kLloyd, kFinal, kFinalizing, kEnded };
+
 struct RJob {
   int64_t id = 0;
   Job* job = nullptr;
   Arena* ar = nullptr;
   int slot = -1;
   int t = 0;             // samples done
+  int stage = kPrep;
   bool lloyd = false;    // the current sample's solve is in the arena
   std::vector<uint8_t> deg_inc, deg_work;
   double f_opt = 0.0;
@@ -337,14 +344,24 @@ bm_status staging_reserve(Staging* g, int64_t s, int d) {
   } while (0)
 
 // Sample t0 + t of job r (Alg. 1): draw, gather, copy the incumbent, reseed
-// its degenerate slots with K-means++ on the sample, and start the solve in
-// the job's arena slot.  Synchronous on `stream`.
-bm_status start_sample(RJob& r, Staging& g, hipStream_t stream) {
+// its degenerate slots with K-means++ on the sample, and lay the sample and
+// the start centroids out in the job's arena slot (its solve state is left
+// to the round thread).  Runs on the prep thread; synchronous on `stream`.
+bm_status prep_sample(RJob& r, Staging& g, hipStream_t stream) {
   const bm_job& J = r.job->spec;
   const bm_options& jo = r.job->opt;
   Arena& A = *r.ar;
   const int d = J.d, k = J.k, dm = A.dm;
   const int64_t s = J.s;
+  if (!r.started) {  // incumbent of a new job: every slot degenerate, or resumed
+    r.started = true;
+    if (jo.resume) {
+      memcpy(r.deg_inc.data(), J.degenerate, static_cast<size_t>(k));
+      r.f_opt = jo.f_opt_in;
+    } else {
+      BM_HIPR(hipMemsetAsync(J.centroids, 0xff, sizeof(float) * k * d, stream));  // NaN rows
+    }
+  }
   const int32_t t = jo.t_start + r.t;
   bm_options o = jo;
   o.stream = stream;
@@ -380,24 +397,32 @@ bm_status start_sample(RJob& r, Staging& g, hipStream_t stream) {
   }
   if ((st = launch_batch_init(Cw, A.c64 + c0 * d, A.Cpad + c0 * dm, k, d, stream)) != BM_OK) return st;
   BM_HIPR(hipMemcpyAsync(A.deg + c0, r.deg_work.data(), static_cast<size_t>(k), hipMemcpyHostToDevice, stream));
+  int bad = 0;
+  BM_HIPR(hipMemcpyAsync(&bad, g.bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+  BM_HIPR(hipStreamSynchronize(stream));
+  if (bad) return set_error(BM_EINVAL, "a sampled index is outside [0, n)");
+  return BM_OK;
+}
+
+// Start the prepared solve of job r in its arena (round thread, between
+// rounds): its state goes to the device on the round stream.
+bm_status activate(RJob& r, hipStream_t stream) {
+  const bm_job& J = r.job->spec;
+  Arena& A = *r.ar;
   BatchSolve& h = A.hs[r.slot];
   const int keep0 = h.tile0, keepn = h.ntiles;
-  if (keepn != static_cast<int>((s + kRoundTile - 1) / kRoundTile)) A.tiles_dirty = true;
+  if (keepn != static_cast<int>((J.s + kRoundTile - 1) / kRoundTile)) A.tiles_dirty = true;
   memset(&h, 0, sizeof h);
-  h.row0 = static_cast<int64_t>(row0);
-  h.s = s;
-  h.c0 = static_cast<int32_t>(c0);
-  h.k = k;
+  h.row0 = static_cast<int64_t>(r.slot) * A.smax;
+  h.s = J.s;
+  h.c0 = static_cast<int32_t>(static_cast<int64_t>(r.slot) * A.kmax);
+  h.k = J.k;
   h.tile0 = keep0;
   h.ntiles = keepn;
   h.status = kSolveRunning;
   h.iter = 1;
   h.f_prev = __builtin_inf();
   BM_HIPR(hipMemcpyAsync(A.sv + r.slot, &h, sizeof(BatchSolve), hipMemcpyHostToDevice, stream));
-  int bad = 0;
-  BM_HIPR(hipMemcpyAsync(&bad, g.bad, sizeof(int), hipMemcpyDeviceToHost, stream));
-  BM_HIPR(hipStreamSynchronize(stream));
-  if (bad) return set_error(BM_EINVAL, "a sampled index is outside [0, n)");
   r.lloyd = true;
   ++A.in_lloyd;
   return BM_OK;
@@ -436,9 +461,9 @@ bm_status arena_round(Arena& A, hipStream_t stream) {
   return BM_OK;
 }
 
-// The solve of job r finished: keep the better centroids (Alg. 1) and move on;
-// after the last sample, the full-data assignment and the outputs.
-bm_status finish_sample(RJob& r, hipStream_t stream) {
+// The solve of job r finished (round thread): keep the better centroids
+// (Alg. 1) and count the sample.  Synchronous on `stream`.
+bm_status keep_best(RJob& r, hipStream_t stream) {
   const bm_job& J = r.job->spec;
   const bm_options& jo = r.job->opt;
   Arena& A = *r.ar;
@@ -458,8 +483,15 @@ bm_status finish_sample(RJob& r, hipStream_t stream) {
     ++r.replacements;
   }
   ++r.t;
-  if (r.t < J.n_samples) return BM_OK;
-  // last sample: full-data assignment (Alg. 1 last step) and the outputs
+  return BM_OK;
+}
+
+// After the last sample (prep thread): the full-data assignment (Alg. 1 last
+// step) and the job's outputs.
+bm_status final_pass(RJob& r, hipStream_t stream) {
+  const bm_job& J = r.job->spec;
+  const bm_options& jo = r.job->opt;
+  const int d = J.d, k = J.k;
   bm_options o = jo;
   o.stream = stream;
   double sse = 0.0;
@@ -477,7 +509,7 @@ bm_status finish_sample(RJob& r, hipStream_t stream) {
     S->struct_size = size;
     S->samples = r.t;
     S->replacements = r.replacements;
-    S->grid = A.grid;
+    S->grid = r.ar->grid;
     S->lloyd_iters = r.iters;
     S->reseeded = r.reseeded;
     S->f_opt = r.f_opt;
@@ -488,19 +520,77 @@ bm_status finish_sample(RJob& r, hipStream_t stream) {
 
 }  // namespace
 
-// The BM_SERVE_ROUNDS engine: admit, start samples, one batched round per
-// class, retire finished samples and jobs; repeat while jobs are in flight.
+// The BM_SERVE_ROUNDS engine.  The round thread (this function) admits jobs,
+// starts prepared solves, runs one batched round per class while any solve
+// runs, keeps the best centroids of finished solves and retires jobs; a prep
+// thread draws, gathers and reseeds samples and runs final passes on its own
+// stream meanwhile, so a job's sample stage does not hold up the others'
+// rounds.  Arena slots are disjoint and a slot's solve is marked done while
+// the prep thread fills it, and the batched kernels skip done solves, so the
+// two streams never touch the same bytes.
 void bm_ctx::engine() {
   Slot& sl = slots[0];
   if (hipSetDevice(device) != hipSuccess) return;
-  scratch_set_thread_pool(&sl.pool);
   std::map<ClassKey, std::unique_ptr<Arena>> arenas;
   std::vector<std::unique_ptr<RJob>> live;
-  Staging stage;
   int64_t arena_bytes = 0;
+  bool prep_stop = false;
+  std::condition_variable cv_prep;
+
+  std::thread prep([&] {
+    if (hipSetDevice(device) != hipSuccess) return;
+    ScratchPool pool;
+    scratch_set_thread_pool(&pool);
+    hipStream_t ps = nullptr;
+    const bool ok = hipStreamCreateWithFlags(&ps, hipStreamNonBlocking) == hipSuccess;
+    Staging stage;
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      RJob* r = nullptr;
+      for (auto& x : live)
+        if (x->stage == kPrep || x->stage == kFinal) {
+          r = x.get();
+          break;
+        }
+      if (!r) {
+        if (prep_stop) break;
+        cv_prep.wait(lk);
+        continue;
+      }
+      const bool fin = r->stage == kFinal;
+      r->stage = fin ? kFinalizing : kPrepping;
+      lk.unlock();
+      clear_error();
+      bm_status st = !ok ? set_error(BM_EDEVICE, "cannot create the prep stream")
+                         : fin ? final_pass(*r, ps) : prep_sample(*r, stage, ps);
+      const std::string msg = st == BM_OK ? "" : bm_last_error();
+      lk.lock();
+      if (st != BM_OK) {
+        r->result = st;
+        snprintf(r->error, sizeof r->error, "%s", msg.c_str());
+        r->stage = kEnded;
+      } else {
+        r->stage = fin ? kEnded : kReady;
+      }
+      cv_work.notify_all();
+    }
+    lk.unlock();
+    if (ps) {
+      (void)hipStreamSynchronize(ps);
+      (void)hipStreamDestroy(ps);
+    }
+    if (stage.idx) (void)hipFree(stage.idx);
+    if (stage.P) (void)hipFree(stage.P);
+    if (stage.bad) (void)hipFree(stage.bad);
+    scratch_pool_free(&pool);
+    scratch_set_thread_pool(nullptr);
+  });
+
+  hipStream_t stream = sl.stream;
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     // admit queued jobs in submission order while a slot is free
+    bool new_prep = false;
     while (!queue.empty() && static_cast<int>(live.size()) < nslots) {
       const int64_t id = queue.front();
       Job* j = jobs[id].get();
@@ -511,19 +601,15 @@ void bm_ctx::engine() {
       const bm_job& J = j->spec;
       const ClassKey key{J.d, j->opt.max_iter, j->opt.stop_rule, j->opt.tol};
       auto it = arenas.find(key);
-      bm_status st = BM_OK;
       if (it == arenas.end()) {
         std::unique_ptr<Arena> A(new Arena());
-        lk.unlock();
         clear_error();
-        st = arena_create(key, nslots, round_max_s, round_max_k, A.get());
-        const std::string msg = st == BM_OK ? "" : bm_last_error();
-        lk.lock();
+        bm_status st = arena_create(key, nslots, round_max_s, round_max_k, A.get());
         if (st == BM_OK && reserved + static_cast<int64_t>(A->bytes) > budget)
           st = set_error(BM_ENOMEM, "a serving arena of %zu bytes exceeds the budget", A->bytes);
         if (st != BM_OK) {
           if (A->mem) (void)hipFree(A->mem);
-          finish_job(j, st, msg.empty() ? bm_last_error() : msg.c_str());
+          finish_job(j, st, bm_last_error());
           cv_done.notify_all();
           continue;
         }
@@ -546,33 +632,56 @@ void bm_ctx::engine() {
       r->deg_inc.assign(J.k, 1);
       r->f_opt = __builtin_inf();
       live.push_back(std::move(r));
+      new_prep = true;
     }
-    if (live.empty()) {
-      if (stopping && queue.empty()) break;
+    if (new_prep) cv_prep.notify_all();
+    // retire ended jobs, freeing their slots
+    for (auto it = live.begin(); it != live.end();) {
+      RJob& r = **it;
+      if (r.stage != kEnded) {
+        ++it;
+        continue;
+      }
+      Arena& A = *r.ar;
+      if (r.lloyd) {  // a failed job's solve is dropped from the next rounds
+        --A.in_lloyd;
+        r.lloyd = false;
+        A.hs[r.slot].status = kSolveDone;
+        (void)hipMemcpyAsync(A.sv + r.slot, &A.hs[r.slot], sizeof(BatchSolve), hipMemcpyHostToDevice, stream);
+        (void)hipStreamSynchronize(stream);
+      }
+      A.owner[r.slot] = -1;
+      A.tiles_dirty = true;
+      finish_job(r.job, r.result, r.error);
+      it = live.erase(it);
+      cv_done.notify_all();
+    }
+    // start prepared solves
+    std::vector<RJob*> ready;
+    int in_lloyd = 0;
+    for (auto& r : live) {
+      if (r->stage == kReady) {
+        r->stage = kLloyd;
+        ready.push_back(r.get());
+      }
+      if (r->stage == kLloyd) ++in_lloyd;
+    }
+    if (in_lloyd == 0) {
+      if (stopping && queue.empty() && live.empty()) break;
       cv_work.wait(lk);
       continue;
     }
     lk.unlock();
 
-    hipStream_t stream = sl.stream;
-    // incumbent of a new job: empty (every slot degenerate), or resumed
-    for (auto& r : live) {
-      if (r->started) continue;
-      r->started = true;
-      const bm_job& J = r->job->spec;
-      if (r->job->opt.resume) {
-        memcpy(r->deg_inc.data(), J.degenerate, static_cast<size_t>(J.k));
-        r->f_opt = r->job->opt.f_opt_in;
-      } else if (hipMemsetAsync(J.centroids, 0xff, sizeof(float) * J.k * J.d, stream) != hipSuccess) {
-        r->result = set_error(BM_EDEVICE, "cannot clear the centroids");
-      }
-    }
-    // sample stage of every job that needs its next sample
-    for (auto& r : live) {
-      if (r->lloyd || r->finished || r->result != BM_OK) continue;
+    std::vector<RJob*> failed, done;
+    for (RJob* r : ready) {
       clear_error();
-      r->result = start_sample(*r, stage, stream);
-      if (r->result != BM_OK) snprintf(r->error, sizeof r->error, "%s", bm_last_error());
+      const bm_status st = activate(*r, stream);
+      if (st != BM_OK) {
+        r->result = st;
+        snprintf(r->error, sizeof r->error, "%s", bm_last_error());
+        failed.push_back(r);
+      }
     }
     // one round per class with running solves
     bm_status rst = BM_OK;
@@ -584,54 +693,46 @@ void bm_ctx::engine() {
     }
     if (rst == BM_OK && hipStreamSynchronize(stream) != hipSuccess)
       rst = set_error(BM_EDEVICE, "a batched round failed");
-    if (rst != BM_OK) {
-      const std::string msg = bm_last_error();
-      for (auto& r : live)
-        if (r->result == BM_OK) {
-          r->result = rst;
-          snprintf(r->error, sizeof r->error, "%s", msg.c_str());
-        }
-    } else {
-      for (auto& r : live) {
-        if (!r->lloyd || r->result != BM_OK) continue;
-        if (r->ar->hs[r->slot].status != kSolveDone) continue;
-        clear_error();
-        r->result = finish_sample(*r, stream);
-        if (r->result != BM_OK) snprintf(r->error, sizeof r->error, "%s", bm_last_error());
-      }
-    }
-
+    const std::string rmsg = rst == BM_OK ? "" : bm_last_error();
     lk.lock();
-    // retire finished and failed jobs, freeing their slots
-    for (auto it = live.begin(); it != live.end();) {
-      RJob& r = **it;
-      if (!r.finished && r.result == BM_OK) {
-        ++it;
+    std::vector<RJob*> lloyd_jobs;
+    for (auto& r : live)
+      if (r->stage == kLloyd && r->result == BM_OK) lloyd_jobs.push_back(r.get());
+    lk.unlock();
+    for (RJob* r : lloyd_jobs) {
+      if (rst != BM_OK) {
+        r->result = rst;
+        snprintf(r->error, sizeof r->error, "%s", rmsg.c_str());
+        failed.push_back(r);
         continue;
       }
-      Arena& A = *r.ar;
-      if (r.lloyd) {
-        --A.in_lloyd;  // a failed job's solve is dropped from the next rounds
-        A.hs[r.slot].status = kSolveDone;
-        (void)hipMemcpyAsync(A.sv + r.slot, &A.hs[r.slot], sizeof(BatchSolve), hipMemcpyHostToDevice, stream);
-        (void)hipStreamSynchronize(stream);
+      if (!r->lloyd || r->ar->hs[r->slot].status != kSolveDone) continue;
+      clear_error();
+      const bm_status st = keep_best(*r, stream);
+      if (st != BM_OK) {
+        r->result = st;
+        snprintf(r->error, sizeof r->error, "%s", bm_last_error());
+        failed.push_back(r);
+      } else {
+        done.push_back(r);
       }
-      A.owner[r.slot] = -1;
-      A.tiles_dirty = true;
-      finish_job(r.job, r.result, r.error);
-      it = live.erase(it);
-      cv_done.notify_all();
     }
+    lk.lock();
+    for (RJob* r : failed) r->stage = kEnded;
+    bool wake_prep = false;
+    for (RJob* r : done) {
+      r->stage = r->t < r->job->spec.n_samples ? kPrep : kFinal;
+      wake_prep = true;
+    }
+    if (wake_prep) cv_prep.notify_all();
   }
+  prep_stop = true;
+  cv_prep.notify_all();
   lk.unlock();
-  (void)hipStreamSynchronize(slots[0].stream);
+  prep.join();
+  (void)hipStreamSynchronize(stream);
   for (auto& kv : arenas)
     if (kv.second->mem) (void)hipFree(kv.second->mem);
-  if (stage.idx) (void)hipFree(stage.idx);
-  if (stage.P) (void)hipFree(stage.P);
-  if (stage.bad) (void)hipFree(stage.bad);
-  scratch_pool_free(&sl.pool);
-  scratch_set_thread_pool(nullptr);
   lk.lock();
   reserved -= arena_bytes;
 }
