@@ -463,6 +463,16 @@ class Server:
             pass
 
 
+def debug_presample(mode):
+    """Test hook: drawing all samples before the solver (0 automatic, 1 never,
+    2 report a window miss so the solver draws them itself); returns the
+    previous mode."""
+    L = load()
+    L.bm_debug_presample.argtypes = [ct.c_int32]
+    L.bm_debug_presample.restype = ct.c_int32
+    return L.bm_debug_presample(mode)
+
+
 def last_rechecked():
     """Points the last BF16-MFMA kmeans_assign on this thread recomputed on the
     FP32 path (near ties)."""

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -17,6 +18,9 @@ namespace bm {
 
 static thread_local char g_err[512] = "";
 static thread_local int64_t g_last_counters[kNumCounters];
+// Presampling before the solver: 0 automatic, 1 never, 2 always report a
+// window miss (the solver then samples itself); a test hook, not in the header.
+static std::atomic<int> g_presample_mode{0};
 static thread_local int64_t g_last_rechecked = 0;
 static thread_local double g_last_assign_ms = 0.0;
 static thread_local int32_t g_last_batch_rounds = 0;
@@ -237,6 +241,7 @@ static void layout_solver(char* base, int64_t n, int64_t s, int d, int k, int T,
   a.sbatch = sbatch;
   a.bar = L.take<GridBarrier>(1);
   a.err = L.take<int32_t>(1);
+  a.presample_miss = L.take<int32_t>(1);
   a.counters = L.take<int64_t>(kNumCounters);
   a.cand_count = L.take<uint32_t>(B);
   a.hist = L.take<uint32_t>(3 * 256);
@@ -378,6 +383,13 @@ int32_t bm_abi_version(void) { return BM_ABI_VERSION; }
 
 // Raw per-phase counters of the last bigmeans_fit on this thread (diagnostics;
 // not declared in the public header).
+// Test hook: presampling mode (0 automatic, 1 never, 2 force a window miss);
+// returns the previous mode.
+int32_t bm_debug_presample(int32_t mode) {
+  if (mode < 0 || mode > 2) return -1;
+  return g_presample_mode.exchange(mode);
+}
+
 int32_t bm_debug_counters(int64_t* out, int32_t n) {
   if (!out || n < 1) return BM_EINVAL;
   for (int i = 0; i < n && i < kNumCounters; ++i) out[i] = g_last_counters[i];
@@ -505,7 +517,10 @@ bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   for (auto& e : ev) BM_HIP(hipEventCreate(&e));
   BM_HIP(hipEventRecord(ev[0], stream));
-  st = launch_solver(a, sp.grid, sp.lds, stream);
+  // every sample drawn up front by ordinary launches when they all have a slot
+  const int pmode = g_presample_mode.load();
+  if (pmode != 1 && a.sbatch == a.T && a.T <= 65535) st = launch_presample(a, sp.lds, stream, pmode == 2);
+  if (st == BM_OK) st = launch_solver(a, sp.grid, sp.lds, stream);
   if (st != BM_OK) {
     for (auto& e : ev) (void)hipEventDestroy(e);
     return st;

@@ -75,6 +75,8 @@ struct SolverArgs {
   uint64_t win_hi;
   uint32_t spin_limit;
   int32_t sbatch;            // samples drawn per batch (slots of the buffers below)
+  int32_t presampled;        // 1: every sample was drawn before the solver launch
+  int32_t* presample_miss;   // 1: a presampled window missed (the solver samples)
   // sample-sized buffers (sbatch slots of each when sampling)
   float* P;                  // sbatch x s x d
   int32_t* idx;              // sbatch x s
@@ -149,6 +151,9 @@ constexpr double kSampleBatchBytes = 256.0 * 1024 * 1024;
 int sample_slots(int64_t n, int64_t s, int d, int T, int64_t cand_cap);
 int padded_dim(int d);
 bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t stream);
+// All a.T samples drawn into their slots by ordinary launches (a.sbatch == a.T);
+// sets a.presampled.
+bm_status launch_presample(SolverArgs& a, size_t lds, hipStream_t stream, bool force_miss = false);
 bm_status solver_max_grid(int dm, size_t lds, int* max_grid);
 bm_status max_lds_per_block(size_t* bytes);
 

@@ -278,9 +278,10 @@ __device__ __forceinline__ void emit_point(const SolverArgs& a, const SBuf& sb, 
 // so workgroup g emits wg_lo[g] plus its candidates that do not exceed the
 // threshold pair.
 __device__ __forceinline__ bool select_threshold(const SolverArgs& a, const SBuf& sb, const LdsPlan& pl,
-                                                 Lds& L, int64_t below, int64_t m, int64_t ppw) {
+                                                 Lds& L, int64_t below, int64_t m, int64_t ppw,
+                                                 int G_ = 0) {
   const int tid = threadIdx.x;
-  const int G = gridDim.x;
+  const int G = G_ > 0 ? G_ : static_cast<int>(gridDim.x);  // workgroups that collected
   unsigned int* hist = reinterpret_cast<unsigned int*>(L.B + pl.hist);
   unsigned int* selc = reinterpret_cast<unsigned int*>(L.B + pl.selc);
   const int64_t need = a.s - below;
@@ -394,7 +395,7 @@ __device__ __forceinline__ bool select_threshold(const SolverArgs& a, const SBuf
 // above (0) the window.  Each thread takes a contiguous run of pairs.
 __device__ __forceinline__ void collect_pass(const SolverArgs& a, const SBuf& sb, const LdsPlan& pl,
                                              Lds& L, uint32_t t, int64_t p0, int64_t p1, uint64_t lo,
-                                             uint64_t hi) {
+                                             uint64_t hi, int g_ = -1) {
   const int tid = threadIdx.x;
   const int64_t n = a.n;
   const int64_t per = (p1 - p0 + kBlock - 1) / kBlock;
@@ -422,12 +423,12 @@ __device__ __forceinline__ void collect_pass(const SolverArgs& a, const SBuf& sb
   }
   flush_candidates(a, sb, pl, L);
   const int wg_lo = block_sum_i32<kBlock>(lo_count, L.tmpi);
-  if (tid == 0) sb.wg_lo[blockIdx.x] = static_cast<uint32_t>(wg_lo);
+  if (tid == 0) sb.wg_lo[g_ >= 0 ? g_ : static_cast<int>(blockIdx.x)] = static_cast<uint32_t>(wg_lo);
 }
 
 // Number of keys below the window over all workgroups (fixed order).
-__device__ __forceinline__ int64_t keys_below(const SBuf& sb, Lds& L) {
-  const int G = gridDim.x;
+__device__ __forceinline__ int64_t keys_below(const SBuf& sb, Lds& L, int G_ = 0) {
+  const int G = G_ > 0 ? G_ : static_cast<int>(gridDim.x);
   const int g0 = 2 * threadIdx.x;
   int v = 0;
   if (g0 < G) v += static_cast<int>(sb.wg_lo[g0]);
@@ -518,9 +519,9 @@ __device__ __forceinline__ bool exact_select(const SolverArgs& a, const SBuf& sb
 // writes them at its offset from one block-wide scan.  No barrier.
 template <int DM>
 __device__ __forceinline__ void emit_sample(const SolverArgs& a, const SBuf& sb, Lds& L, uint32_t t,
-                                            int tt, int64_t p0, int64_t p1) {
+                                            int tt, int64_t p0, int64_t p1, int g_ = -1) {
   const int tid = threadIdx.x;
-  const int g = blockIdx.x;
+  const int g = g_ >= 0 ? g_ : static_cast<int>(blockIdx.x);
   const int64_t n = a.n;
   const uint64_t tk = sb.thr[0];
   const int64_t ti = static_cast<int64_t>(sb.thr[1]);
@@ -1325,11 +1326,15 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
   float* const Pb = a.P;
   int32_t* const idxb = a.idx;
   bool stored = false;  // the previous sample replaced the incumbent (grid-uniform)
+  // every sample was drawn before this launch (presample_* kernels) unless a
+  // predicted window missed; then the samples are drawn here as usual
+  const bool presampled =
+      a.presampled && __hip_atomic_load(a.presample_miss, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
   for (int tt = 0; ok && tt < a.T; ++tt) {
     const uint32_t t = static_cast<uint32_t>(a.t0 + tt);
     const int slot = tt % a.sbatch;
     uint64_t clk0 = wall_clock64();
-    if (a.do_sample && slot == 0) {
+    if (a.do_sample && slot == 0 && !presampled) {
       const int nb = a.T - tt < a.sbatch ? a.T - tt : a.sbatch;
       ok = sample_batch<DM>(a, pl, L, Pb, idxb, tt, nb, c_hist);
       if (!ok) break;
@@ -1410,6 +1415,65 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
     a.counters[kCntTicksPass] = static_cast<int64_t>(c_tpass);
     a.counters[kCntTicksPost] = static_cast<int64_t>(c_tpost);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Presampling: every sample of a fit drawn before the persistent solver starts,
+// by three ordinary launches over the whole device (a sample depends only on
+// (seed, t)), when all of a fit's samples fit the sample buffers.  Workgroup
+// (g, b) takes chunk g of the point pairs of sample b; the selection is the
+// solver's own (collect, threshold select, emit in index order), with `gp`
+// chunks in place of the solver's workgroups, so the samples are the same.  A
+// sample whose predicted window misses raises *presample_miss, and the solver
+// then draws every sample itself.
+
+template <int DM>
+__global__ void __launch_bounds__(kBlock) presample_collect_kernel(SolverArgs a, int gp) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds != 0, a.c64_in_lds != 0);
+  Lds L = carve(lds_raw, pl);
+  const int g = blockIdx.x, b = blockIdx.y;
+  const int64_t npairs = (a.n + 1) >> 1;
+  const int64_t ppw = (npairs + gp - 1) / gp;
+  const int64_t p0 = imin64(npairs, static_cast<int64_t>(g) * ppw);
+  const int64_t p1 = imin64(npairs, p0 + ppw);
+  collect_pass(a, slot_bufs(a, a.P, a.idx, b), pl, L, static_cast<uint32_t>(a.t0 + b), p0, p1, a.win_lo,
+               a.win_hi, g);
+}
+
+template <int DM>
+__global__ void __launch_bounds__(kBlock) presample_select_kernel(SolverArgs a, int gp) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds != 0, a.c64_in_lds != 0);
+  Lds L = carve(lds_raw, pl);
+  const int b = blockIdx.x;
+  const int64_t npairs = (a.n + 1) >> 1;
+  const int64_t ppw = (npairs + gp - 1) / gp;
+  const SBuf sb = slot_bufs(a, a.P, a.idx, b);
+  const int64_t below = keys_below(sb, L, gp);
+  const int64_t m = __hip_atomic_load(sb.cand_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const bool hit = m <= a.cand_cap && below < a.s && a.s <= below + m;
+  if (hit) {
+    (void)select_threshold(a, sb, pl, L, below, m, ppw, gp);  // an inconsistency sets the error
+  } else if (threadIdx.x == 0) {
+    __hip_atomic_store(a.presample_miss, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(sb.cand_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int DM>
+__global__ void __launch_bounds__(kBlock) presample_emit_kernel(SolverArgs a, int gp) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  if (__hip_atomic_load(a.presample_miss, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds != 0, a.c64_in_lds != 0);
+  Lds L = carve(lds_raw, pl);
+  const int g = blockIdx.x, b = blockIdx.y;
+  const int64_t npairs = (a.n + 1) >> 1;
+  const int64_t ppw = (npairs + gp - 1) / gp;
+  const int64_t p0 = imin64(npairs, static_cast<int64_t>(g) * ppw);
+  const int64_t p1 = imin64(npairs, p0 + ppw);
+  emit_sample<DM>(a, slot_bufs(a, a.P, a.idx, b), L, static_cast<uint32_t>(a.t0 + b), b, p0, p1, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -1499,6 +1563,47 @@ bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t s
   if (e != hipSuccess)
     return set_error(BM_EDEVICE, "cooperative launch failed (grid %d, LDS %zu B): %s", grid, lds,
                      hipGetErrorString(e));
+  return BM_OK;
+}
+
+// Draw all a.T samples into their slots before the solver (see the
+// presample kernels); the caller has checked a.sbatch == a.T.
+bm_status launch_presample(SolverArgs& a, size_t lds, hipStream_t stream, bool force_miss) {
+  const int dm = padded_dim(a.d);
+  const void* fc = nullptr;
+  const void* fs = nullptr;
+  const void* fe = nullptr;
+  switch (dm) {
+#define BM_PRE(D)                                                        \
+  case D:                                                                \
+    fc = reinterpret_cast<const void*>(&presample_collect_kernel<D>);    \
+    fs = reinterpret_cast<const void*>(&presample_select_kernel<D>);     \
+    fe = reinterpret_cast<const void*>(&presample_emit_kernel<D>);       \
+    break;
+    BM_PRE(4) BM_PRE(8) BM_PRE(16) BM_PRE(32) BM_PRE(64) BM_PRE(72) BM_PRE(128) BM_PRE(256)
+#undef BM_PRE
+    default: return set_error(BM_ENOTSUP, "dimension %d exceeds the solver's limit of 256", a.d);
+  }
+  if (a.sbatch != a.T || a.T < 1 || a.T > 65535 || !a.presample_miss)
+    return set_error(BM_EINVAL, "presampling needs every sample in its own slot");
+  const int64_t npairs = (a.n + 1) >> 1;
+  int64_t gp = (npairs + 4095) / 4096;  // ~8 pairs per thread
+  if (gp < 1) gp = 1;
+  if (gp > kMaxGrid) gp = kMaxGrid;
+  if (lds > 65536) {
+    for (const void* f : {fc, fs, fe})
+      if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+        return set_error(BM_ENOTSUP, "cannot reserve %zu B of LDS for presampling", lds);
+  }
+  SolverArgs copy = a;
+  int g32 = static_cast<int>(gp);
+  void* args[] = {&copy, &g32};
+  hipError_t e = hipLaunchKernel(fc, dim3(g32, a.T), dim3(kBlock), args, lds, stream);
+  if (e == hipSuccess) e = hipLaunchKernel(fs, dim3(a.T), dim3(kBlock), args, lds, stream);
+  if (e == hipSuccess && force_miss) e = hipMemsetAsync(a.presample_miss, 1, 1, stream);  // test hook
+  if (e == hipSuccess) e = hipLaunchKernel(fe, dim3(g32, a.T), dim3(kBlock), args, lds, stream);
+  if (e != hipSuccess) return set_error(BM_EDEVICE, "presample launch failed: %s", hipGetErrorString(e));
+  a.presampled = 1;
   return BM_OK;
 }
 

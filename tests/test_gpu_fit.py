@@ -157,3 +157,24 @@ def test_k_equals_s_equals_n():
     got = bigmeans.bigmeans_fit(torch.from_numpy(X).cuda(), 12, 12, 2, 1)
     assert got["sse"] == 0.0
     assert not got["degenerate"].any()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_presampled_and_in_kernel_samples_agree(mode):
+    # all samples drawn before the solver (automatic) vs. drawn by the solver
+    # (presampling off, or a reported window miss): the same samples (Sec. 3.2
+    # keys) and so the same fit
+    from paper_2204_07485_amd import bigmeans
+    W = synth.SMALL
+    X = torch.from_numpy(synth.make_small()).cuda()
+    kw = dict(sample_idx=True, max_iter=100, tol=1e-4, stop_rule=bigmeans.BM_STOP_SHIFT)
+    ref = bigmeans.bigmeans_fit(X, W.k, W.s, W.n_samples, W.seed, **kw)
+    prev = bigmeans.debug_presample(mode)
+    try:
+        got = bigmeans.bigmeans_fit(X, W.k, W.s, W.n_samples, W.seed, **kw)
+    finally:
+        bigmeans.debug_presample(prev)
+    assert torch.equal(got["sample_idx"], ref["sample_idx"])
+    assert np.array_equal(got["degenerate"], ref["degenerate"])
+    np.testing.assert_allclose(got["sample_f"], ref["sample_f"], rtol=1e-9)
+    assert_sse(got["sse"], ref["sse"])
