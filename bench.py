@@ -357,7 +357,7 @@ def main():
         "sse_rel_err_max": max(rel),
         "fit_ms_p50": float(np.percentile(wall, 50)),
         "fit_ms_p99": float(np.percentile(wall, 99)),
-        "roofline": {"bound": "hbm", "kernel": "solver_kernel<16> (sample loop)",
+        "roofline": {"bound": "hbm", "kernel": "sample loop: presample_collect/select/emit<16> + solver_kernel<16>",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_solver,
                      "ms_per_launch": solver_ms, "algorithmic_bytes": solver_bytes,
