@@ -147,7 +147,7 @@ size_t solver_lds_bytes(int dm, int k, int d, bool sums_in_lds, bool c64_in_lds)
 void sampler_window(int64_t n, int64_t s, uint64_t* lo, uint64_t* hi, int64_t* cap);
 // Samples drawn per batch by bigmeans_fit: all T when their buffers (rows,
 // indices, codes, candidates) fit in kSampleBatchBytes, else fewer (>= 1).
-constexpr double kSampleBatchBytes = 256.0 * 1024 * 1024;
+constexpr double kSampleBatchBytes = 4096.0 * 1024 * 1024;
 int sample_slots(int64_t n, int64_t s, int d, int T, int64_t cand_cap);
 int padded_dim(int d);
 bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t stream);
