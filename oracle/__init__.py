@@ -4,7 +4,12 @@ TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
 baseline leg of the benchmark, never by the GPU library or its binding.
 Arrays are numpy; X is float32 (or uint16 holding BF16 bits), centroids are
 float64, degenerate centroids are NaN rows with deg[j] = 1.
+
+Every function runs the single-threaded build unless called inside
+``with oracle.threaded():``, which switches to the OpenMP build (same source,
+bit-identical results; for timing on all host cores and for large workloads).
 """
+import contextlib
 import ctypes as ct
 import os
 
@@ -12,7 +17,8 @@ import numpy as np
 
 from . import build_oracle
 
-_LIB = None
+_LIBS = {}
+_THREADED = False
 
 ORC_F32, ORC_BF16 = 0, 1
 ORC_STOP_SHIFT, ORC_STOP_REL_OBJ = 0, 1
@@ -35,14 +41,15 @@ class Stats(ct.Structure):
 
 
 def lib():
-    global _LIB
-    if _LIB is None:
-        path = build_oracle.LIB
-        src = os.path.join(os.path.dirname(path), "bm_oracle.c")
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+    """The oracle library in use (single-threaded, or OpenMP inside threaded())."""
+    key = "omp" if _THREADED else "serial"
+    if key not in _LIBS:
+        path = build_oracle.LIB_OMP if _THREADED else build_oracle.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(build_oracle.SRC):
             build_oracle.build()
         L = ct.CDLL(path)
         P = ct.c_void_p
+        L.orc_threads.restype = ct.c_int
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_seed_word.argtypes = [ct.c_uint64, ct.c_uint32, ct.c_uint64]
         L.orc_seed_word.restype = ct.c_uint64
@@ -53,6 +60,8 @@ def lib():
         L.orc_dist2.restype = ct.c_double
         L.orc_assign.argtypes = [P, ct.c_int64, ct.c_int32, P, P, ct.c_int32, P, P]
         L.orc_assign.restype = ct.c_double
+        L.orc_d2_pick.argtypes = [P, ct.c_int64, ct.c_double]
+        L.orc_d2_pick.restype = ct.c_int64
         L.orc_kmeanspp.argtypes = [P, ct.c_int64, ct.c_int32, ct.c_int32, P, P,
                                    ct.c_uint64, ct.c_uint32, ct.c_int32, P]
         L.orc_lloyd.argtypes = [P, ct.c_int64, ct.c_int32, ct.c_int32, P, P, P, P, P, P]
@@ -60,8 +69,25 @@ def lib():
         L.orc_bigmeans_fit.argtypes = [P, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32,
                                        ct.c_int64, ct.c_int32, ct.c_uint64, P,
                                        ct.c_int32, ct.c_int32, P, P, P, P, P, P, P, P]
-        _LIB = L
-    return _LIB
+        _LIBS[key] = L
+    return _LIBS[key]
+
+
+@contextlib.contextmanager
+def threaded():
+    """Run the oracle calls inside this block on the OpenMP build."""
+    global _THREADED
+    prev = _THREADED
+    _THREADED = True
+    try:
+        yield
+    finally:
+        _THREADED = prev
+
+
+def threads():
+    """Threads the library in use runs its per-point loops on."""
+    return int(lib().orc_threads())
 
 
 def _p(a):
@@ -113,6 +139,12 @@ def assign(P, C, deg=None):
     mind = np.zeros(s, dtype=np.float64)
     f = lib().orc_assign(_p(P), s, d, _p(C), _p(dg), k, _p(labels), _p(mind))
     return labels, mind, f
+
+
+def d2_pick(w, target):
+    """One D^2 draw by inverting the running sum of w at target."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    return int(lib().orc_d2_pick(_p(w), w.shape[0], float(target)))
 
 
 def kmeanspp(P, C, deg, seed, t, trials=3):

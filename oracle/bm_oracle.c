@@ -3,8 +3,15 @@
  *
  * TEST INFRASTRUCTURE ONLY (see bm_oracle.h).  Written for a reader holding the
  * paper: every step follows the passage named in its comment, in the paper's
- * order, with no blocking, fusion or reordering.  Single-threaded on purpose,
- * so every sum has one fixed order.
+ * order, with no blocking, fusion or reordering.  Every sum has one fixed
+ * order: the index order of its terms.
+ *
+ * Threads: the same source builds a single-threaded library and an OpenMP one
+ * (-fopenmp; used to time the oracle on all host cores and to compute stored
+ * results of large workloads).  Only loops whose iterations are independent
+ * per point are shared out (distances, keys, row loads); each writes its
+ * per-point terms to an array, and every sum over points is then taken by one
+ * thread in index order.  So both builds return bit-identical results.
  *
  * Random stream (the paper names no generator; this is the fixed reading):
  *   Philox4x32-10, key = (low 32 bits of seed, high 32 bits of seed), counter
@@ -23,6 +30,19 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the per-point loops use (1 in the single-threaded build). */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  One round multiplies
@@ -113,6 +133,7 @@ int orc_sample(int64_t n, int64_t s, uint64_t seed, uint32_t t, int32_t* idx)
     if (n < 1 || s < 1 || s > n || n > 2147483647LL) return -1;
     keyed* all = (keyed*)malloc((size_t)n * sizeof(keyed));
     if (!all) return -2;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         all[i].key = orc_sample_key(seed, t, i);
         all[i].i = i;
@@ -141,7 +162,8 @@ double orc_dist2(const double* x, const double* c, int32_t d)
 double orc_assign(const double* P, int64_t s, int32_t d, const double* C,
                   const uint8_t* deg, int32_t k, int32_t* labels, double* mind)
 {
-    double f = 0.0;
+    double* md = mind ? mind : (double*)malloc((size_t)s * sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < s; ++i) {
         const double* x = P + (size_t)i * d;
         int32_t best = -1;
@@ -152,9 +174,11 @@ double orc_assign(const double* P, int64_t s, int32_t d, const double* C,
             if (dd < bestd) { bestd = dd; best = j; }
         }
         if (labels) labels[i] = best;
-        if (mind) mind[i] = bestd;
-        f += bestd;
+        md[i] = bestd;
     }
+    double f = 0.0;
+    for (int64_t i = 0; i < s; ++i) f += md[i];
+    if (!mind) free(md);
     return f;
 }
 
@@ -175,17 +199,34 @@ static int32_t count_active(const uint8_t* deg, int32_t k)
  * order; among the candidates the one with the smallest potential
  * sum_i min(D_i^2, |p_i - c|^2) wins, ties to the earlier draw; if every D^2
  * is zero the remaining slots stay degenerate.                              */
+/* One D^2 draw: the smallest row i whose running sum w_0 + ... + w_i (added
+ * in row order) exceeds target; if rounding leaves no such row, the last row
+ * with w_i > 0; -1 if every w_i is zero.                                    */
+int64_t orc_d2_pick(const double* w, int64_t s, double target)
+{
+    double run = 0.0;
+    for (int64_t i = 0; i < s; ++i) {
+        run += w[i];
+        if (run > target) return i;
+    }
+    for (int64_t i = s - 1; i >= 0; --i)
+        if (w[i] > 0.0) return i;
+    return -1;
+}
+
 int orc_kmeanspp(const double* P, int64_t s, int32_t d, int32_t k, double* C,
                  uint8_t* deg, uint64_t seed, uint32_t t, int32_t trials,
                  orc_stats* st)
 {
     if (s < 1 || d < 1 || k < 1 || trials < 1) return -1;
     double* w = (double*)malloc((size_t)s * sizeof(double));
-    if (!w) return -2;
+    double* term = (double*)malloc((size_t)s * sizeof(double));
+    if (!w || !term) { free(w); free(term); return -2; }
     uint64_t q = 0;
     int32_t active = count_active(deg, k);
 
     if (active > 0) {
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < s; ++i) {
             double best = INFINITY;
             for (int32_t j = 0; j < k; ++j) {
@@ -211,28 +252,23 @@ int orc_kmeanspp(const double* P, int64_t s, int32_t d, int32_t k, double* C,
             double best_phi = INFINITY;
             for (int32_t l = 0; l < trials; ++l) {
                 double target = word_to_unit(orc_seed_word(seed, t, q++)) * W;
-                int64_t cand = -1;
-                double run = 0.0;
-                for (int64_t i = 0; i < s; ++i) {
-                    run += w[i];
-                    if (run > target) { cand = i; break; }
-                }
-                if (cand < 0) {
-                    for (int64_t i = s - 1; i >= 0; --i)
-                        if (w[i] > 0.0) { cand = i; break; }
-                }
+                int64_t cand = orc_d2_pick(w, s, target);
                 if (trials == 1) { pick = cand; break; }
-                double phi = 0.0;
+                /* potential of the candidate: sum_i min(w_i, |p_i - cand|^2) */
+#pragma omp parallel for schedule(static)
                 for (int64_t i = 0; i < s; ++i) {
                     double dd = orc_dist2(P + (size_t)i * d, P + (size_t)cand * d, d);
-                    phi += dd < w[i] ? dd : w[i];
+                    term[i] = dd < w[i] ? dd : w[i];
                 }
+                double phi = 0.0;
+                for (int64_t i = 0; i < s; ++i) phi += term[i];
                 if (st) st->n_d += s;
                 if (phi < best_phi) { best_phi = phi; pick = cand; }
             }
         }
         memcpy(C + (size_t)j * d, P + (size_t)pick * d, (size_t)d * sizeof(double));
         deg[j] = 0;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < s; ++i) {
             double dd = orc_dist2(P + (size_t)i * d, C + (size_t)j * d, d);
             if (active == 0 || dd < w[i]) w[i] = dd;
@@ -241,6 +277,7 @@ int orc_kmeanspp(const double* P, int64_t s, int32_t d, int32_t k, double* C,
         active += 1;
     }
     free(w);
+    free(term);
     return 0;
 }
 
@@ -355,8 +392,7 @@ int orc_bigmeans_fit(const void* X, int32_t x_dtype, int64_t n, int32_t d,
     double* P = (double*)malloc((size_t)s * d * sizeof(double));
     double* Cp = (double*)malloc((size_t)k * d * sizeof(double));
     uint8_t* degp = (uint8_t*)malloc((size_t)k);
-    double* row = (double*)malloc((size_t)d * sizeof(double));
-    if (!idx || !P || !Cp || !degp || !row) return -2;
+    if (!idx || !P || !Cp || !degp) return -2;
 
     if (!resume) {
         for (size_t z = 0; z < (size_t)k * d; ++z) C[z] = NAN;
@@ -368,6 +404,7 @@ int orc_bigmeans_fit(const void* X, int32_t x_dtype, int64_t n, int32_t d,
         uint32_t t = (uint32_t)(t_start + tt);
         orc_sample(n, s, seed, t, idx);
         if (sample_idx) memcpy(sample_idx + (size_t)tt * s, idx, (size_t)s * sizeof(int32_t));
+#pragma omp parallel for schedule(static)
         for (int64_t r = 0; r < s; ++r) load_row(X, x_dtype, idx[r], d, P + (size_t)r * d);
 
         memcpy(Cp, C, (size_t)k * d * sizeof(double));
@@ -394,22 +431,32 @@ int orc_bigmeans_fit(const void* X, int32_t x_dtype, int64_t n, int32_t d,
     }
 
     if (labels || sse) {
-        double total = 0.0;
-        for (int64_t i = 0; i < n; ++i) {
-            load_row(X, x_dtype, i, d, row);
-            int32_t best = -1;
-            double bestd = INFINITY;
-            for (int32_t j = 0; j < k; ++j) {
-                if (deg[j]) continue;
-                double dd = orc_dist2(row, C + (size_t)j * d, d);
-                if (dd < bestd) { bestd = dd; best = j; }
+        double* md = (double*)malloc((size_t)n * sizeof(double));
+        if (!md) return -2;
+#pragma omp parallel
+        {
+            double* xr = (double*)malloc((size_t)d * sizeof(double));
+#pragma omp for schedule(static)
+            for (int64_t i = 0; i < n; ++i) {
+                load_row(X, x_dtype, i, d, xr);
+                int32_t best = -1;
+                double bestd = INFINITY;
+                for (int32_t j = 0; j < k; ++j) {
+                    if (deg[j]) continue;
+                    double dd = orc_dist2(xr, C + (size_t)j * d, d);
+                    if (dd < bestd) { bestd = dd; best = j; }
+                }
+                if (labels) labels[i] = best;
+                md[i] = bestd;
             }
-            if (labels) labels[i] = best;
-            total += bestd;
+            free(xr);
         }
+        double total = 0.0;
+        for (int64_t i = 0; i < n; ++i) total += md[i];
+        free(md);
         if (sse) *sse = total;
     }
     if (st) st->f_opt = *f_opt;
-    free(idx); free(P); free(Cp); free(degp); free(row);
+    free(idx); free(P); free(Cp); free(degp);
     return 0;
 }

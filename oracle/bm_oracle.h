@@ -54,6 +54,10 @@ typedef struct orc_stats {
     double  f_opt;          /* incumbent objective on its own sample          */
 } orc_stats;
 
+/* Threads the per-point loops use: 1, or OpenMP's count in the threaded
+ * build (whose results are bit-identical to the single-threaded build's). */
+int orc_threads(void);
+
 /* Philox4x32 with 10 rounds (Salmon et al., SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* 64-bit word of the draw-stream block q of sample t (stream tag 1). */
@@ -70,6 +74,10 @@ double orc_dist2(const double* x, const double* c, int32_t d);
 /* Nearest active centroid of every row; returns the SSE (index-order sum). */
 double orc_assign(const double* P, int64_t s, int32_t d, const double* C,
                   const uint8_t* deg, int32_t k, int32_t* labels, double* mind);
+
+/* One D^2 draw: the smallest i whose running sum of w (row order) exceeds
+ * target; if none does (rounding), the last i with w[i] > 0; -1 if all zero. */
+int64_t orc_d2_pick(const double* w, int64_t s, double target);
 
 /* K-means++ reseed of the slots with deg[j] = 1 on the rows of P. */
 int orc_kmeanspp(const double* P, int64_t s, int32_t d, int32_t k, double* C,
