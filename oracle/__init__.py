@@ -23,12 +23,13 @@ _THREADED = False
 ORC_F32, ORC_BF16 = 0, 1
 ORC_STOP_SHIFT, ORC_STOP_REL_OBJ = 0, 1
 ORC_CMP_FOPT, ORC_CMP_RESAMPLE = 0, 1
+ORC_INIT_KMEANSPP, ORC_INIT_FORGY = 0, 1
 
 
 class Opts(ct.Structure):
     _fields_ = [("max_iter", ct.c_int32), ("tol", ct.c_double),
                 ("stop_rule", ct.c_int32), ("n_local_trials", ct.c_int32),
-                ("compare_rule", ct.c_int32)]
+                ("compare_rule", ct.c_int32), ("init_method", ct.c_int32)]
 
 
 class Stats(ct.Structure):
@@ -69,6 +70,15 @@ def lib():
         L.orc_bigmeans_fit.argtypes = [P, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32,
                                        ct.c_int64, ct.c_int32, ct.c_uint64, P,
                                        ct.c_int32, ct.c_int32, P, P, P, P, P, P, P, P]
+        L.orc_forgy.argtypes = [P, ct.c_int64, ct.c_int32, ct.c_int32, P, P, ct.c_uint64,
+                                ct.c_uint32, P]
+        L.orc_bigmeans_collective.argtypes = [P, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32,
+                                              ct.c_int64, ct.c_int32, ct.c_int32, ct.c_uint64, P,
+                                              P, P, P, P, P, P, P]
+        L.orc_sample_size_sweep.argtypes = [P, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32,
+                                            ct.c_int64, ct.c_int64, ct.c_int32, ct.c_uint64, P,
+                                            P, P, P]
+        L.orc_sample_size_sweep.restype = ct.c_int64
         _LIBS[key] = L
     return _LIBS[key]
 
@@ -95,8 +105,8 @@ def _p(a):
 
 
 def make_opts(max_iter=100, tol=1e-4, stop_rule=ORC_STOP_SHIFT, n_local_trials=3,
-              compare_rule=ORC_CMP_FOPT):
-    return Opts(max_iter, tol, stop_rule, n_local_trials, compare_rule)
+              compare_rule=ORC_CMP_FOPT, init_method=ORC_INIT_KMEANSPP):
+    return Opts(max_iter, tol, stop_rule, n_local_trials, compare_rule, init_method)
 
 
 def philox(ctr, key):
@@ -161,6 +171,19 @@ def kmeanspp(P, C, deg, seed, t, trials=3):
     return C, deg, st.as_dict()
 
 
+def forgy(P, C, deg, seed, t):
+    """Forgy-style reinitialisation of the slots with deg[j] = 1; returns (C, deg, stats)."""
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    C = np.array(C, dtype=np.float64, copy=True)
+    deg = np.array(deg, dtype=np.uint8, copy=True)
+    s, d = P.shape
+    st = Stats()
+    rc = lib().orc_forgy(_p(P), s, d, C.shape[0], _p(C), _p(deg), seed, t, ct.byref(st))
+    if rc != 0:
+        raise ValueError(f"orc_forgy failed ({rc})")
+    return C, deg, st.as_dict()
+
+
 def lloyd(P, C, deg, max_iter=100, tol=1e-4, stop_rule=ORC_STOP_SHIFT):
     """Lloyd from C on P; returns (C, deg, labels, f, passes, stats)."""
     P = np.ascontiguousarray(P, dtype=np.float64)
@@ -179,7 +202,7 @@ def lloyd(P, C, deg, max_iter=100, tol=1e-4, stop_rule=ORC_STOP_SHIFT):
 def bigmeans_fit(X, k, s, n_samples, seed, max_iter=100, tol=1e-4,
                  stop_rule=ORC_STOP_SHIFT, n_local_trials=3, compare_rule=ORC_CMP_FOPT,
                  t_start=0, state=None, want_labels=True, want_sse=True,
-                 want_sample_idx=False, x_dtype=None):
+                 want_sample_idx=False, x_dtype=None, init_method=ORC_INIT_KMEANSPP):
     """Big-means (Alg. 1).  X: float32 (n, d), or uint16 BF16 bits with x_dtype=ORC_BF16.
 
     state: optional (C, deg, f_opt) incumbent to resume from.
@@ -189,7 +212,7 @@ def bigmeans_fit(X, k, s, n_samples, seed, max_iter=100, tol=1e-4,
         x_dtype = ORC_BF16 if X.dtype == np.uint16 else ORC_F32
     X = np.ascontiguousarray(X)
     n, d = X.shape
-    o = make_opts(max_iter, tol, stop_rule, n_local_trials, compare_rule)
+    o = make_opts(max_iter, tol, stop_rule, n_local_trials, compare_rule, init_method)
     if state is not None:
         C = np.array(state[0], dtype=np.float64, copy=True)
         deg = np.array(state[1], dtype=np.uint8, copy=True)
@@ -215,3 +238,49 @@ def bigmeans_fit(X, k, s, n_samples, seed, max_iter=100, tol=1e-4,
             "sse": sse.value if want_sse else None, "sample_f": sample_f[:n_samples],
             "sample_idx": None if sample_idx is None else sample_idx[:n_samples],
             "stats": st.as_dict()}
+
+
+def _x_dtype(X, x_dtype):
+    if x_dtype is None:
+        x_dtype = ORC_BF16 if X.dtype == np.uint16 else ORC_F32
+    return np.ascontiguousarray(X), x_dtype
+
+
+def bigmeans_collective(X, k, s, n_workers, n_rounds, seed, max_iter=100, tol=1e-4,
+                        stop_rule=ORC_STOP_SHIFT, n_local_trials=3, init_method=ORC_INIT_KMEANSPP,
+                        want_labels=True, x_dtype=None):
+    """Collective parallel Big-means (Sec. 3.6, third scheme).  Returns a dict
+    with C, deg, f_opt, labels, sse, worker_f (rounds x workers), stats."""
+    X, x_dtype = _x_dtype(X, x_dtype)
+    n, d = X.shape
+    o = make_opts(max_iter, tol, stop_rule, n_local_trials, ORC_CMP_FOPT, init_method)
+    C = np.zeros((k, d), dtype=np.float64)
+    deg = np.ones(k, dtype=np.uint8)
+    f_opt = ct.c_double(0.0)
+    labels = np.zeros(n, dtype=np.int32) if want_labels else None
+    sse = ct.c_double(0.0)
+    wf = np.zeros((n_rounds, n_workers), dtype=np.float64)
+    st = Stats()
+    rc = lib().orc_bigmeans_collective(_p(X), x_dtype, n, d, k, s, n_workers, n_rounds, seed,
+                                       ct.byref(o), _p(C), _p(deg), ct.byref(f_opt), _p(labels),
+                                       ct.byref(sse), _p(wf), ct.byref(st))
+    if rc != 0:
+        raise ValueError(f"orc_bigmeans_collective failed ({rc})")
+    return {"C": C, "deg": deg, "f_opt": f_opt.value, "labels": labels, "sse": sse.value,
+            "worker_f": wf, "stats": st.as_dict()}
+
+
+def sample_size_sweep(X, k, s_min, s_max, n_samples, seed, max_iter=100, tol=1e-4,
+                      stop_rule=ORC_STOP_SHIFT, n_local_trials=3, x_dtype=None):
+    """The sample-size rule of thumb (Sec. 5).  Returns (best s, [(s, sse), ...])."""
+    X, x_dtype = _x_dtype(X, x_dtype)
+    n, d = X.shape
+    o = make_opts(max_iter, tol, stop_rule, n_local_trials)
+    s_tried = np.zeros(64, dtype=np.int64)
+    sse_tried = np.zeros(64, dtype=np.float64)
+    m = ct.c_int32(0)
+    best = lib().orc_sample_size_sweep(_p(X), x_dtype, n, d, k, s_min, s_max, n_samples, seed,
+                                       ct.byref(o), _p(s_tried), _p(sse_tried), ct.byref(m))
+    if best < 0:
+        raise ValueError(f"orc_sample_size_sweep failed ({best})")
+    return int(best), [(int(s_tried[i]), float(sse_tried[i])) for i in range(m.value)]

@@ -282,6 +282,28 @@ int orc_kmeanspp(const double* P, int64_t s, int32_t d, int32_t k, double* C,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Another initialisation (Sec. 3.3: the first sample may be initialised
+ * otherwise, e.g. at random, and degenerate clusters may be handled by other
+ * strategies): every degenerate slot, in ascending order, takes the row of P
+ * at a uniformly drawn index -- independent draws, so two slots may take the
+ * same row; the later one then empties and is reinitialised at the next
+ * sample.  Draw q of sample t is the same stream word K-means++ uses.        */
+int orc_forgy(const double* P, int64_t s, int32_t d, int32_t k, double* C,
+              uint8_t* deg, uint64_t seed, uint32_t t, orc_stats* st)
+{
+    if (s < 1 || d < 1 || k < 1) return -1;
+    uint64_t q = 0;
+    for (int32_t j = 0; j < k; ++j) {
+        if (!deg[j]) continue;
+        int64_t pick = (int64_t)word_below(orc_seed_word(seed, t, q++), (uint64_t)s);
+        memcpy(C + (size_t)j * d, P + (size_t)pick * d, (size_t)d * sizeof(double));
+        deg[j] = 0;
+        if (st) st->reseeded += 1;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* K-means / Lloyd (Sec. 2): assign, then move each centre to the mean of its
  * cell.  Stop rules: ORC_STOP_REL_OBJ is the rule of Sec. 5 (stop when the
  * relative decrease of two consecutive objective values is below tol, or after
@@ -370,6 +392,9 @@ static void load_row(const void* X, int32_t x_dtype, int64_t i, int32_t d, doubl
     }
 }
 
+static double final_pass(const void* X, int32_t x_dtype, int64_t n, int32_t d, int32_t k,
+                         const double* C, const uint8_t* deg, int32_t* labels);
+
 /* Big-means, Alg. 1 (Sec. 3.2): start with every centroid degenerate and
  * f_opt = infinity; per sample draw P, copy the incumbent, reseed its
  * degenerate centroids with K-means++, run K-means on P, and replace the
@@ -409,8 +434,12 @@ int orc_bigmeans_fit(const void* X, int32_t x_dtype, int64_t n, int32_t d,
 
         memcpy(Cp, C, (size_t)k * d * sizeof(double));
         memcpy(degp, deg, (size_t)k);
-        if (count_active(degp, k) < k)
-            orc_kmeanspp(P, s, d, k, Cp, degp, seed, t, o->n_local_trials, st);
+        if (count_active(degp, k) < k) {
+            if (o->init_method == ORC_INIT_FORGY)
+                orc_forgy(P, s, d, k, Cp, degp, seed, t, st);
+            else
+                orc_kmeanspp(P, s, d, k, Cp, degp, seed, t, o->n_local_trials, st);
+        }
 
         double f = orc_lloyd(P, s, d, k, Cp, degp, o, NULL, NULL, st);
         if (sample_f) sample_f[tt] = f;
@@ -431,32 +460,141 @@ int orc_bigmeans_fit(const void* X, int32_t x_dtype, int64_t n, int32_t d,
     }
 
     if (labels || sse) {
-        double* md = (double*)malloc((size_t)n * sizeof(double));
-        if (!md) return -2;
-#pragma omp parallel
-        {
-            double* xr = (double*)malloc((size_t)d * sizeof(double));
-#pragma omp for schedule(static)
-            for (int64_t i = 0; i < n; ++i) {
-                load_row(X, x_dtype, i, d, xr);
-                int32_t best = -1;
-                double bestd = INFINITY;
-                for (int32_t j = 0; j < k; ++j) {
-                    if (deg[j]) continue;
-                    double dd = orc_dist2(xr, C + (size_t)j * d, d);
-                    if (dd < bestd) { bestd = dd; best = j; }
-                }
-                if (labels) labels[i] = best;
-                md[i] = bestd;
-            }
-            free(xr);
-        }
-        double total = 0.0;
-        for (int64_t i = 0; i < n; ++i) total += md[i];
-        free(md);
+        double total = final_pass(X, x_dtype, n, d, k, C, deg, labels);
         if (sse) *sse = total;
     }
     if (st) st->f_opt = *f_opt;
     free(idx); free(P); free(Cp); free(degp);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Final assignment (Alg. 1 last step, Sec. 3.4) of every row of X to the
+ * nearest active centroid; returns the objective on X (index-order sum).    */
+static double final_pass(const void* X, int32_t x_dtype, int64_t n, int32_t d, int32_t k,
+                         const double* C, const uint8_t* deg, int32_t* labels)
+{
+    double* md = (double*)malloc((size_t)n * sizeof(double));
+    if (!md) return NAN;
+#pragma omp parallel
+    {
+        double* xr = (double*)malloc((size_t)d * sizeof(double));
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            load_row(X, x_dtype, i, d, xr);
+            int32_t best = -1;
+            double bestd = INFINITY;
+            for (int32_t j = 0; j < k; ++j) {
+                if (deg[j]) continue;
+                double dd = orc_dist2(xr, C + (size_t)j * d, d);
+                if (dd < bestd) { bestd = dd; best = j; }
+            }
+            if (labels) labels[i] = best;
+            md[i] = bestd;
+        }
+        free(xr);
+    }
+    double total = 0.0;
+    for (int64_t i = 0; i < n; ++i) total += md[i];
+    free(md);
+    return total;
+}
+
+/* Collective parallel Big-means (Sec. 3.6, third scheme; see bm_oracle.h).
+ * Each worker of a round does what one sample of Alg. 1 does, starting from
+ * the same incumbent; the round's best worker result then goes through
+ * Alg. 1's keep-the-best comparison.                                        */
+int orc_bigmeans_collective(const void* X, int32_t x_dtype, int64_t n, int32_t d,
+                            int32_t k, int64_t s, int32_t W, int32_t R, uint64_t seed,
+                            const orc_opts* o, double* C, uint8_t* deg, double* f_opt,
+                            int32_t* labels, double* sse, double* worker_f,
+                            orc_stats* st)
+{
+    if (n < 1 || d < 1 || k < 1 || s < k || s > n || W < 1 || R < 1) return -1;
+    if (n > 2147483647LL || o->max_iter < 1 || o->n_local_trials < 1) return -1;
+    if ((int64_t)R * W > 4294967295LL) return -1;
+    int32_t* idx = (int32_t*)malloc((size_t)s * sizeof(int32_t));
+    double* P = (double*)malloc((size_t)s * d * sizeof(double));
+    double* Cw = (double*)malloc((size_t)k * d * sizeof(double));
+    uint8_t* degw = (uint8_t*)malloc((size_t)k);
+    double* Cbest = (double*)malloc((size_t)k * d * sizeof(double));
+    uint8_t* degbest = (uint8_t*)malloc((size_t)k);
+    if (!idx || !P || !Cw || !degw || !Cbest || !degbest) return -2;
+
+    for (size_t z = 0; z < (size_t)k * d; ++z) C[z] = NAN;
+    memset(deg, 1, (size_t)k);
+    *f_opt = INFINITY;
+
+    for (int32_t r = 0; r < R; ++r) {
+        double round_best = INFINITY;
+        for (int32_t w = 0; w < W; ++w) {
+            uint32_t t = (uint32_t)((int64_t)r * W + w);
+            orc_sample(n, s, seed, t, idx);
+#pragma omp parallel for schedule(static)
+            for (int64_t q = 0; q < s; ++q) load_row(X, x_dtype, idx[q], d, P + (size_t)q * d);
+            memcpy(Cw, C, (size_t)k * d * sizeof(double));
+            memcpy(degw, deg, (size_t)k);
+            if (count_active(degw, k) < k) {
+                if (o->init_method == ORC_INIT_FORGY)
+                    orc_forgy(P, s, d, k, Cw, degw, seed, t, st);
+                else
+                    orc_kmeanspp(P, s, d, k, Cw, degw, seed, t, o->n_local_trials, st);
+            }
+            double f = orc_lloyd(P, s, d, k, Cw, degw, o, NULL, NULL, st);
+            if (worker_f) worker_f[(size_t)r * W + w] = f;
+            if (st) st->samples += 1;
+            if (f < round_best) {      /* strict: ties go to the lowest worker */
+                round_best = f;
+                memcpy(Cbest, Cw, (size_t)k * d * sizeof(double));
+                memcpy(degbest, degw, (size_t)k);
+            }
+        }
+        if (*f_opt > round_best) {
+            memcpy(C, Cbest, (size_t)k * d * sizeof(double));
+            memcpy(deg, degbest, (size_t)k);
+            *f_opt = round_best;
+            if (st) st->replacements += 1;
+        }
+    }
+    if (labels || sse) {
+        double total = final_pass(X, x_dtype, n, d, k, C, deg, labels);
+        if (sse) *sse = total;
+    }
+    if (st) st->f_opt = *f_opt;
+    free(idx); free(P); free(Cw); free(degw); free(Cbest); free(degbest);
+    return 0;
+}
+
+/* The sample-size rule of thumb of Sec. 5 (see bm_oracle.h): grow s by
+ * doubling while the final objective on X keeps decreasing.                 */
+int64_t orc_sample_size_sweep(const void* X, int32_t x_dtype, int64_t n, int32_t d,
+                              int32_t k, int64_t s_min, int64_t s_max, int32_t T,
+                              uint64_t seed, const orc_opts* o, int64_t* s_tried,
+                              double* sse_tried, int32_t* n_tried)
+{
+    if (s_min < k || s_min > s_max || T < 1) return -1;
+    if (s_max > n) s_max = n;
+    if (s_min > s_max) return -1;
+    double* C = (double*)malloc((size_t)k * d * sizeof(double));
+    uint8_t* deg = (uint8_t*)malloc((size_t)k);
+    if (!C || !deg) return -2;
+    int64_t best_s = -1;
+    double best = INFINITY;
+    int32_t m = 0;
+    for (int64_t s = s_min;; ) {
+        double f_opt = 0.0, sse = 0.0;
+        int rc = orc_bigmeans_fit(X, x_dtype, n, d, k, s, T, seed, o, 0, 0, C, deg, &f_opt,
+                                  NULL, &sse, NULL, NULL, NULL);
+        if (rc != 0) { free(C); free(deg); return -3; }
+        if (m < 64) { s_tried[m] = s; sse_tried[m] = sse; }
+        ++m;
+        if (!(sse < best)) break;          /* no improvement: the sweet spot is behind */
+        best = sse;
+        best_s = s;
+        if (s >= s_max || m >= 64) break;
+        s = (s > s_max / 2) ? s_max : 2 * s;
+    }
+    *n_tried = m < 64 ? m : 64;
+    free(C); free(deg);
+    return best_s;
 }

@@ -36,6 +36,7 @@ extern "C" {
 enum { ORC_F32 = 0, ORC_BF16 = 1 };
 enum { ORC_STOP_SHIFT = 0, ORC_STOP_REL_OBJ = 1 };
 enum { ORC_CMP_FOPT = 0, ORC_CMP_RESAMPLE = 1 };
+enum { ORC_INIT_KMEANSPP = 0, ORC_INIT_FORGY = 1 };
 
 typedef struct orc_opts {
     int32_t max_iter;       /* Lloyd assign+update rounds per sample          */
@@ -43,6 +44,8 @@ typedef struct orc_opts {
     int32_t stop_rule;      /* ORC_STOP_SHIFT | ORC_STOP_REL_OBJ              */
     int32_t n_local_trials; /* K-means++ candidates per new centre (>= 1)     */
     int32_t compare_rule;   /* ORC_CMP_FOPT | ORC_CMP_RESAMPLE                */
+    int32_t init_method;    /* ORC_INIT_KMEANSPP | ORC_INIT_FORGY: how the    */
+                            /* degenerate centroids are (re)initialised       */
 } orc_opts;
 
 typedef struct orc_stats {
@@ -84,6 +87,12 @@ int orc_kmeanspp(const double* P, int64_t s, int32_t d, int32_t k, double* C,
                  uint8_t* deg, uint64_t seed, uint32_t t, int32_t trials,
                  orc_stats* st);
 
+/* Forgy-style (re)initialisation of the slots with deg[j] = 1: each takes a
+ * uniformly drawn row of P, slots in ascending order, draws from the same
+ * stream as K-means++ (Sec. 3.3 allows initialisations other than K-means++). */
+int orc_forgy(const double* P, int64_t s, int32_t d, int32_t k, double* C,
+              uint8_t* deg, uint64_t seed, uint32_t t, orc_stats* st);
+
 /* Lloyd from C on P; returns the SSE of the returned C on P. */
 double orc_lloyd(const double* P, int64_t s, int32_t d, int32_t k, double* C,
                  uint8_t* deg, const orc_opts* o, int32_t* labels,
@@ -100,6 +109,29 @@ int orc_bigmeans_fit(const void* X, int32_t x_dtype, int64_t n, int32_t d,
                      double* C, uint8_t* deg, double* f_opt, int32_t* labels,
                      double* sse, double* sample_f, int32_t* sample_idx,
                      orc_stats* st);
+
+/* Collective parallel Big-means (Sec. 3.6, third scheme): W workers per
+ * round, worker w of round r clusters sample t = r*W + w starting from the
+ * incumbent of the previous rounds (all degenerate in round 0); after each
+ * round the worker with the smallest f(C'',P) (ties to the lowest w) replaces
+ * the incumbent when its objective is below f_opt.  R rounds, then the final
+ * assignment.  worker_f (R*W, may be NULL) gets every worker's f(C'',P). */
+int orc_bigmeans_collective(const void* X, int32_t x_dtype, int64_t n, int32_t d,
+                            int32_t k, int64_t s, int32_t W, int32_t R, uint64_t seed,
+                            const orc_opts* o, double* C, uint8_t* deg, double* f_opt,
+                            int32_t* labels, double* sse, double* worker_f,
+                            orc_stats* st);
+
+/* The sample-size rule of thumb (Sec. 5): s = s_min, 2 s_min, 4 s_min, ...
+ * (capped at s_max and n), one Big-means run of T samples each with its final
+ * objective on X, continued while the objective decreases; stops at the
+ * first s that does not improve on the best so far.  s_tried / sse_tried get
+ * the sizes run and their objectives (capacity 64), *n_tried their count;
+ * returns the best s (or < 0 on bad arguments). */
+int64_t orc_sample_size_sweep(const void* X, int32_t x_dtype, int64_t n, int32_t d,
+                              int32_t k, int64_t s_min, int64_t s_max, int32_t T,
+                              uint64_t seed, const orc_opts* o, int64_t* s_tried,
+                              double* sse_tried, int32_t* n_tried);
 
 #ifdef __cplusplus
 }
