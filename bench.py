@@ -70,60 +70,83 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-samples", type=int, default=12,
-                    help="samples the CPU oracle runs for its bounded baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solves workload")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the BF16 workload's mixed-precision (MFMA) comparison")
+    ap.add_argument("--no-final", action="store_true",
+                    help="skip the cache-flushed final-pass timings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a plain 1 GiB device copy three times (a known "
                          "amount of HBM traffic for scaling profiler byte counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(X, W, n_cpu_samples):
-    """The oracle as it stands, single-threaded, on a bounded sample of the
-    workload: the first n_cpu_samples samples of the fit, plus one full final
-    assignment pass, scaled to the full fit."""
-    import numpy as np
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def cpu_baseline(X, W):
+    """The oracle as it stands, in its OpenMP build (per-point loops on all
+    host cores, every sum in index order, results bit-identical to the
+    single-threaded build), timed on the whole fit: all samples plus the
+    final assignment pass."""
     import oracle
-    t0 = time.perf_counter()
-    r = oracle.bigmeans_fit(X, W.k, W.s, n_cpu_samples, W.seed, max_iter=300, tol=1e-4,
-                            stop_rule=oracle.ORC_STOP_REL_OBJ, want_labels=False,
-                            want_sse=False)
-    t_samples = time.perf_counter() - t0
-    C = np.where(np.isnan(r["C"]), 0.0, r["C"])
-    t1 = time.perf_counter()
-    oracle.assign(X, C, r["deg"])
-    t_final = time.perf_counter() - t1
-    ms = (t_samples / n_cpu_samples * W.n_samples + t_final) * 1e3
-    return {"value": ms, "unit": "ms", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_cpu_samples} of {W.n_samples} samples ({t_samples:.1f} s) "
-                      f"scaled to {W.n_samples}, plus one full final pass ({t_final:.1f} s)"}
+    with oracle.threaded():
+        threads = oracle.threads()
+        t0 = time.perf_counter()
+        r = oracle.bigmeans_fit(X, W.k, W.s, W.n_samples, W.seed, max_iter=300, tol=1e-4,
+                                stop_rule=oracle.ORC_STOP_REL_OBJ, want_labels=True, want_sse=True)
+        secs = time.perf_counter() - t0
+    return {"value": secs * 1e3, "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"the whole fit ({W.n_samples} samples + final pass), OpenMP oracle build on "
+                      f"{threads} threads; host: {os.cpu_count()} logical CPUs, {cpu_model()}",
+            "oracle_sse": r["sse"]}
+
+
+def flush_mall(buf):
+    """Read a buffer larger than the 256 MB last-level cache so the next
+    kernel finds none of its input there."""
+    import torch
+    buf.add_(1.0)
+    torch.cuda.synchronize()
 
 
 def mixed_precision(reps=5):
     """The BF16 workload (5,000,000 x 128 BF16, 100 components + 10% outliers,
     k=100, s=200,000, 30 samples, seed 4): one full fit per distance
-    arithmetic (the final pass differs), then the final assignment pass alone
-    timed with HIP events for both forms on the fit's centroids."""
+    arithmetic, each checked against the oracle's stored result, then the final
+    assignment pass alone timed with HIP events for both forms on the fit's
+    centroids."""
     import numpy as np
     import torch
 
     from paper_2204_07485_amd import bigmeans, synth
     W = synth.BF16
+    with open(os.path.join(ROOT, "tests", "golden", "bf16_fit.json")) as fh:
+        gold = json.load(fh)
     H = synth.make_bf16()
     Hd = torch.from_numpy(H.view(np.int16)).to("cuda:0")
     del H
     kw = dict(max_iter=300, tol=1e-4, stop_rule=bigmeans.BM_STOP_REL_OBJ, n_local_trials=3)
     fits = {}
     for name, prec in (("fp32", bigmeans.BM_PREC_FP32), ("bf16_mfma", bigmeans.BM_PREC_BF16_MFMA)):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = bigmeans.bigmeans_fit(Hd, W.k, W.s, W.n_samples, W.seed, precision=prec, **kw)
-        fits[name] = (r, (time.perf_counter() - t0) * 1e3)
+        bigmeans.bigmeans_fit(Hd, W.k, W.s, 2, W.seed, precision=prec, **kw)  # warm-up
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = bigmeans.bigmeans_fit(Hd, W.k, W.s, W.n_samples, W.seed, precision=prec, **kw)
+            ms = (time.perf_counter() - t0) * 1e3
+            best = (r, ms) if best is None or ms < best[1] else best
+        fits[name] = best
     C, deg = fits["bf16_mfma"][0]["centroids"], fits["bf16_mfma"][0]["degenerate"]
     ms = {}
     out = {}
@@ -138,11 +161,17 @@ def mixed_precision(reps=5):
     algo_bytes = n * d * 2 + n * 4
     kp = 16 * ((k + 15) // 16)
     gbs = algo_bytes / (ms["bf16_mfma"] * 1e-3) / 1e9
+    rel = {name: abs(v[0]["sse"] - gold["sse"]) / gold["sse"] for name, v in fits.items()}
     return {
         "workload": "bf16: 5,000,000 x 128 BF16 Gaussian mixture (100 components, sigma "
                     "U[0.5,2], 10% uniform outliers), k=100, s=200,000, 30 samples, seed 4",
         "fit_ms": {k_: v[1] for k_, v in fits.items()},
+        "time_to_oracle_sse_ms": {k_: (v[1] if rel[k_] <= 1e-6 else None) for k_, v in fits.items()},
         "fit_sse": {k_: v[0]["sse"] for k_, v in fits.items()},
+        "oracle_sse": gold["sse"],
+        "fit_sse_rel_err": rel,
+        "fit_ms_solver": {k_: v[0]["stats"]["ms_solver"] for k_, v in fits.items()},
+        "fit_ms_final": {k_: v[0]["stats"]["ms_final"] for k_, v in fits.items()},
         "final_pass_ms": ms,
         "final_pass_speedup": ms["fp32"] / ms["bf16_mfma"],
         "labels_equal": bool((out["fp32"][0] == out["bf16_mfma"][0]).all()),
@@ -154,6 +183,47 @@ def mixed_precision(reps=5):
                      "mfma_tflops": 2 * 2 * n * kp * d / (ms["bf16_mfma"] * 1e-3) / 1e12,
                      "fp32_path_tflops": 2 * n * k * d / (ms["fp32"] * 1e-3) / 1e12},
     }
+
+
+def final_passes(Xmed, gold, reps=5):
+    """The full-data assignment pass (Alg. 1 last step) timed alone with HIP
+    events, with the last-level cache flushed before each launch: the medium
+    workload at its fitted centroids, and the batched workload's 10,000,000 x
+    68 data (2.72 GB) at k = 50 (C = 50 of its rows)."""
+    import numpy as np
+    import torch
+
+    from paper_2204_07485_amd import bigmeans, synth
+    flush = torch.zeros(1 << 27, dtype=torch.float32, device="cuda:0")  # 512 MB
+    res = {}
+    Cm = np.array([[np.nan if v is None else v for v in row] for row in gold["C"]], np.float32)
+    degm = np.array(gold["deg"], np.uint8)
+    cases = [("medium_1Mx16_k25", Xmed, torch.from_numpy(Cm).cuda(), degm)]
+    Xw = torch.from_numpy(synth.make_wide()).to("cuda:0")
+    rows = np.random.default_rng(3).choice(Xw.shape[0], 50, replace=False)
+    cases.append(("wide_10Mx68_k50", Xw, Xw[torch.from_numpy(rows).cuda()].contiguous(),
+                  np.zeros(50, np.uint8)))
+    for name, X, C, deg in cases:
+        n, d = X.shape
+        k = C.shape[0]
+        vals = []
+        for _ in range(reps):
+            flush_mall(flush)
+            bigmeans.kmeans_assign(X, C, deg)
+            vals.append(bigmeans.last_assign_ms())
+        warm = []
+        for _ in range(reps):
+            bigmeans.kmeans_assign(X, C, deg)
+            warm.append(bigmeans.last_assign_ms())
+        ms = statistics.median(vals)
+        algo = n * d * 4 + n * 4
+        res[name] = {"kernel": f"assign_kernel<{ {16: 16, 68: 72}[d] },f32>", "ms_cold": ms,
+                     "ms_warm": statistics.median(warm), "algorithmic_bytes": algo,
+                     "gbs_cold": algo / (ms * 1e-3) / 1e9, "hbm_frac_cold": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "tflops_cold": 2 * n * k * d / (ms * 1e-3) / 1e12}
+    del Xw, flush
+    torch.cuda.empty_cache()
+    return res
 
 
 def batched_solves(n_seq=16):
@@ -190,8 +260,10 @@ def batched_solves(n_seq=16):
         _, _, _, sp = bigmeans.kmeans_lloyd(P[r0[j]:r0[j + 1]], Cj, deg[c0[j]:c0[j + 1]], **kw)
         seq_rows += sp * s[j]
     seq_ms = (time.perf_counter() - t1) * 1e3
-    # first round: every solve active, the full sample set streamed once
-    first_bytes = float(s.sum()) * 72 * 4  # rows are read padded to 72 columns
+    # first round: every solve active, the full sample set streamed once;
+    # algorithmic bytes count the 68 stored columns (the kernel reads rows
+    # zero-padded to 72 columns, 6 % more)
+    first_bytes = float(s.sum()) * d * 4
     first_ms = info["round_ms"][0]
     gbs = first_bytes / (first_ms * 1e-3) / 1e9
     return {
@@ -204,6 +276,8 @@ def batched_solves(n_seq=16):
         "speedup_vs_sequential": (rows_passes / wall) / (seq_rows / seq_ms),
         "roofline_first_round": {"bound": "alu", "kernel": "batch_assign_kernel<72,true>",
                                  "achieved_gbs": gbs, "peak_gbs": HBM_PEAK_GBS,
+                                 "algorithmic_bytes": first_bytes,
+                                 "padded_bytes_read": float(s.sum()) * 72 * 4,
                                  "hbm_frac": gbs / HBM_PEAK_GBS, "ms": first_ms,
                                  "tflops": float((s * k).sum()) * 68 * 2 / (first_ms * 1e-3) / 1e12,
                                  "fp32_direct_difference_peak_tflops": FP32_DD_PEAK_TFLOPS},
@@ -377,6 +451,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if not args.no_final:
+        print("final passes (cache flushed) ...", file=sys.stderr, flush=True)
+        line["final_pass"] = final_passes(Xd, gold)
     if not args.no_mixed:
         print("mixed precision: BF16 workload ...", file=sys.stderr, flush=True)
         line["mixed_precision"] = mixed_precision()
@@ -387,8 +464,8 @@ def main():
         print("serving stream ...", file=sys.stderr, flush=True)
         line["serving"] = serve_stream()
     if not args.no_cpu_baseline:
-        print("cpu baseline (oracle, 1 thread) ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(X, W, args.cpu_samples)
+        print("cpu baseline (oracle, all host cores) ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(X, W)
     print(json.dumps(line), flush=True)
 
 

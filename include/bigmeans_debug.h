@@ -1,0 +1,50 @@
+/*
+ * bigmeans_debug.h -- diagnostics and test hooks of libbigmeans.so.
+ *
+ * Not part of the clustering API (bigmeans.h): these report per-thread
+ * details of the last call for tests and measurement, or switch internal
+ * paths so tests can reach them.  All are thread-safe in the sense that they
+ * read or write only the calling thread's records (bm_debug_presample is
+ * process-wide).
+ */
+#ifndef BIGMEANS_DEBUG_H
+#define BIGMEANS_DEBUG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Presampling before the persistent solver: mode 0 = automatic, 1 = never
+ * (the solver draws every sample), 2 = report a predicted-window miss (the
+ * solver then draws every sample itself).  Returns the previous mode, or -1
+ * for a mode outside 0..2.  Process-wide. */
+int32_t bm_debug_presample(int32_t mode);
+
+/* Copies the first n raw device counters of this thread's last bigmeans_fit
+ * (passes, reseeds, replacements, n_d, boundary draws, samples, sampler
+ * passes, then per-phase clock ticks) into out.  BM_EINVAL for out NULL or
+ * n < 1. */
+int32_t bm_debug_counters(int64_t* out, int32_t n);
+
+/* Points this thread's last BM_PREC_BF16_MFMA kmeans_assign recomputed on
+ * the FP32 path (near ties). */
+int64_t bm_debug_rechecked(void);
+
+/* Device time in ms (HIP events on the call's stream, bracketing only the
+ * assignment kernel) of this thread's last kmeans_assign. */
+double bm_debug_assign_ms(void);
+
+/* Rounds and rows per work tile of this thread's last kmeans_lloyd_batched;
+ * either pointer may be NULL.  Returns 0. */
+int32_t bm_debug_batch_info(int32_t* rounds, int32_t* tile_rows);
+
+/* Device time in ms of round i of this thread's last kmeans_lloyd_batched
+ * (0 when i is out of range). */
+double bm_debug_batch_round_ms(int32_t i);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BIGMEANS_DEBUG_H */

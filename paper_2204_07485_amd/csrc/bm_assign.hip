@@ -50,7 +50,9 @@ __global__ void __launch_bounds__(kAssignBlock)
 
   double sse = 0.0;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kAssignBlock;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kAssignBlock + tid; i < n; i += stride) {
+  // with no active centroid (a failed fit) the outputs are left untouched
+  const int64_t n_rows = na > 0 ? n : 0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kAssignBlock + tid; i < n_rows; i += stride) {
     float x[DM];
     if (BF16) {
       load_row_bf16<DM>(static_cast<const uint16_t*>(Xv) + static_cast<size_t>(i) * d, d, x);
@@ -131,6 +133,12 @@ bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float
   if (st != BM_OK) return st;
   if (lds + 1024 > lds_max)
     return set_error(BM_ENOTSUP, "k*d = %d*%d centroids do not fit in LDS", k, d);
+  if (lds > 65536) {
+    const hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              static_cast<int>(lds));
+    if (ea != hipSuccess)
+      return set_error(BM_EDEVICE, "assign LDS attribute: %s", hipGetErrorString(ea));
+  }
   void* args[] = {const_cast<void**>(&X), &n, &d, const_cast<float**>(&C),
                   const_cast<uint8_t**>(&deg_dev), &k, &labels, &min_d2, &partial, &done,
                   &sse_dev};

@@ -115,6 +115,7 @@ __global__ void __launch_bounds__(kBatchBlock)
       int bj;
       float bd;
       nearest_f32_sgpr<DM>(x, Cpad + static_cast<size_t>(c0) * DM, act, na, bj, bd);
+      if (bj < 0) continue;  // no active centroid: nothing to assign or add
       if (labels && !dry) labels[i] = bj;
       const float* cw = Cl + bj * DM;
       if (accumulate) {

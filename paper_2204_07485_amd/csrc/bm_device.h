@@ -276,7 +276,8 @@ template <int DM>
 __device__ __forceinline__ void nearest_f32(const float (&x)[DM], const float* __restrict__ Cl,
                                             const int* __restrict__ act, int na, int& best_j,
                                             float& best_d) {
-  best_j = -1;
+  // a row whose distances are all NaN or +inf still gets a valid slot
+  best_j = na > 0 ? act[0] : -1;
   best_d = __builtin_inff();
   for (int a = 0; a < na; ++a) {
     const int j = act[a];
@@ -301,7 +302,8 @@ template <int DM>
 __device__ __forceinline__ void nearest_f32_sgpr(const float (&x)[DM], const float* __restrict__ Cpad,
                                                  const int* __restrict__ act, int na, int& best_j,
                                                  float& best_d) {
-  best_j = -1;
+  // a row whose distances are all NaN or +inf still gets a valid slot
+  best_j = na > 0 ? __builtin_amdgcn_readfirstlane(act[0]) : -1;
   best_d = __builtin_inff();
   for (int a = 0; a < na; ++a) {
     const int j = __builtin_amdgcn_readfirstlane(act[a]);

@@ -34,6 +34,27 @@ def top2_gap(P, C, deg=None, chunk=1 << 16):
     return out
 
 
+def near_tie_count(P, C, deg=None, chunk=1 << 15):
+    """Number of rows whose two nearest active centroids are within the
+    near-tie band, from FP64 distances by the norm expansion (fast; only used
+    to bound how far cluster sizes may move between two correct runs)."""
+    P = np.asarray(P)
+    C = np.asarray(C, dtype=np.float64)
+    act = np.ones(len(C), bool) if deg is None else ~np.asarray(deg, bool)
+    Ca = C[act]
+    if len(Ca) < 2:
+        return 0
+    cn = (Ca * Ca).sum(axis=1)
+    total = 0
+    for lo in range(0, len(P), chunk):
+        x = np.asarray(P[lo:lo + chunk], dtype=np.float64)
+        D = (x * x).sum(axis=1)[:, None] - 2.0 * (x @ Ca.T) + cn[None, :]
+        part = np.partition(D, 1, axis=1)
+        d1, d2 = part[:, 0], part[:, 1]
+        total += int(((d2 - d1) < 2 * LABEL_TIE_REL * np.maximum(d2, 1e-300)).sum())
+    return total
+
+
 def assert_labels(got, ref, P, C, deg=None):
     """Labels equal except at near ties of the oracle's distances; returns
     the number of (allowed) mismatches."""

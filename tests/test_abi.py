@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI (no GPU): the library loads, exports every
-function include/bigmeans.h declares, and rejects invalid arguments with
-BM_EINVAL before touching the device."""
+function include/bigmeans.h and include/bigmeans_debug.h declare and nothing
+else of C linkage, and rejects invalid arguments with BM_EINVAL before
+touching the device."""
 import ctypes as ct
 import os
 import re
@@ -10,12 +11,23 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "bigmeans.h")
+DEBUG_HEADER = os.path.join(ROOT, "include", "bigmeans_debug.h")
 
 
-def _declared_functions():
-    text = open(HEADER).read()
+def _declared_functions(path=HEADER):
+    text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:bm_status|const char\*|int32_t)\s+(\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:bm_status|const char\*|int32_t|int64_t|double)\s+(\w+)\s*\(",
+                                 text, re.M)))
+
+
+def _exported_c_symbols(path):
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", path], check=True, capture_output=True,
+                         text=True).stdout
+    names = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    # C++ symbols are mangled (_Z...); __hip_cuid_* identify the code objects
+    return sorted(n for n in names if not n.startswith("_Z") and not n.startswith("__hip_cuid_"))
 
 
 @pytest.fixture(scope="module")
@@ -31,6 +43,15 @@ def test_library_exports_every_declared_function(bm):
     for name in names:
         assert hasattr(lib, name), name
     assert set(names) == set(bm.FUNCTIONS)
+
+
+def test_every_exported_symbol_is_declared(bm):
+    bm.load()
+    declared = set(_declared_functions(HEADER)) | set(_declared_functions(DEBUG_HEADER))
+    exported = set(_exported_c_symbols(bm.LIB_PATH))
+    assert exported == declared, (sorted(exported - declared), sorted(declared - exported))
+    for name in _declared_functions(DEBUG_HEADER):
+        assert name.startswith("bm_debug_"), name
 
 
 def test_abi_version_and_struct_sizes(bm):

@@ -79,3 +79,32 @@ def test_assign_full_medium_workload():
     ref_lab, _, ref_sse = oracle.assign(X, C)
     assert_sse(sse, ref_sse)
     assert_labels(lab.cpu().numpy(), ref_lab, X, C)
+
+
+def test_assign_fp32_centroids_beyond_64k_lds():
+    # k x d = 128 x 128 FP32 centroids (64 KiB + flags) need the large-LDS launch attribute
+    from paper_2204_07485_amd import bigmeans
+    X = _mixture(30_000, 128, 128, seed=9)
+    C = X[np.random.default_rng(9).choice(len(X), 128, replace=False)].astype(np.float32) + 0.1
+    lab, _, sse = bigmeans.kmeans_assign(torch.from_numpy(X).cuda(), torch.from_numpy(C).cuda())
+    ref_lab, _, ref_sse = oracle.assign(X, C)
+    assert_labels(lab.cpu().numpy(), ref_lab, X, C)
+    assert_sse(sse, ref_sse)
+
+
+def test_assign_nonfinite_rows_get_a_valid_label():
+    # a row with a NaN or an infinite coordinate has no nearest centroid; it
+    # still gets an active slot, and the other rows are unaffected
+    from paper_2204_07485_amd import bigmeans
+    X = _mixture(2_000, 8, 4, seed=10)
+    X[5, 3] = np.nan
+    X[17, 0] = np.inf
+    C = X[[0, 1, 2, 3]].copy()
+    deg = np.array([1, 0, 0, 0], np.uint8)
+    lab, _, _ = bigmeans.kmeans_assign(torch.from_numpy(X).cuda(), torch.from_numpy(C).cuda(), deg)
+    lab = lab.cpu().numpy()
+    assert lab[5] == 1 and lab[17] == 1
+    ok = np.ones(len(X), bool)
+    ok[[5, 17]] = False
+    ref_lab, _, _ = oracle.assign(X[ok], C, deg)
+    assert_labels(lab[ok], ref_lab, X[ok], C, deg)

@@ -88,6 +88,40 @@ def _compare(P, C0, deg0, got, ref, strict):
         assert abs(gf - rf) <= 0.05 * rf
 
 
+# Problems (by index in `specs`) whose oracle trajectory comes within the
+# near-tie band, per parametrisation; computed from the oracle alone.  Only
+# these take the relaxed whole-run check (after a lock-step check of the
+# batched kernels along the oracle's path), and only when the strict one fails.
+NEAR_TIE_PROBLEMS = {(2, 1, 300): {5, 8}, (16, 0, 100): {4, 5, 8}, (68, 1, 300): {2, 4, 5, 6, 8},
+                     (5, 0, 1): {5}, (128, 1, 50): {4, 5, 8}}
+
+
+def _lockstep_batched(P, C0, deg0, steps):
+    """The batched kernels started from every oracle iterate (one round each):
+    the update must equal the oracle's, unless the oracle's assignment at that
+    iterate has a near tie (then a flipped point may move a centroid); the
+    labels returned for the updated centroids are their nearest ones."""
+    C = np.asarray(C0, np.float64)
+    deg = np.array(deg0, np.uint8)
+    for _ in range(steps):
+        C32 = C.astype(np.float32)
+        got, _ = _run_batched([(P, C32, deg)], max_iter=1, tol=0.0)
+        gC, gdeg, glab, gf, gp = got[0]
+        assert gp == 2
+        rC, rdeg, rlab, _, _, _ = oracle.lloyd(P, C32, deg, max_iter=1, tol=0.0)
+        near = (~deg.astype(bool)).sum() > 1 and float(top2_gap(P, C32, deg).min()) < LABEL_TIE_REL
+        try:
+            assert np.array_equal(gdeg, rdeg)
+            assert_centroids(gC, rC, rdeg, P, rlab)
+        except AssertionError:
+            if not near:
+                raise
+        assert_labels(glab, oracle.assign(P, gC, gdeg)[0], P, gC, gdeg)
+        if np.allclose(rC, C, equal_nan=True, rtol=0, atol=0):
+            break
+        C, deg = rC, rdeg
+
+
 @pytest.mark.parametrize("d,rule,max_iter", [(2, 1, 300), (16, 0, 100), (68, 1, 300), (5, 0, 1),
                                              (128, 1, 50)])
 def test_batched_matches_single_and_oracle(d, rule, max_iter):
@@ -103,6 +137,17 @@ def test_batched_matches_single_and_oracle(d, rule, max_iter):
         rC, rdeg, rlab, rf, rp, _ = oracle.lloyd(P, C0, deg0, **kw)
         gap = _oracle_min_gap(P, C0, deg0, steps=min(rp, 60))
         strict = gap >= LABEL_TIE_REL
+        assert strict == (j not in NEAR_TIE_PROBLEMS[(d, rule, max_iter)]), f"near-tie status of {j}"
+        if not strict:
+            _lockstep_batched(P, C0, deg0, steps=min(rp, 20))
+            try:
+                _compare(P, C0, deg0, got[j], (rC, rdeg, rlab, rf, rp), True)
+                print(f"  problem {j}: near tie on the oracle path; whole run still equal",
+                      flush=True)
+                continue
+            except AssertionError:
+                print(f"  problem {j}: near tie on the oracle path; trajectories diverged",
+                      flush=True)
         _compare(P, C0, deg0, got[j], (rC, rdeg, rlab, rf, rp), strict)
         if strict:
             # and against the single-problem GPU path, integer results exactly
@@ -141,8 +186,9 @@ def test_batched_degenerate_input_flags_are_kept():
 
 def test_batched_wide_workload_sampled():
     # a quarter of the batched workload's solves (64 of 256) on its full-size
-    # data (10,000,000 x 68), set up as the benchmark does; 4 solves are
-    # checked against the single-problem path
+    # data (10,000,000 x 68), set up as the benchmark does; 6 solves are
+    # checked against the single-problem path and against the oracle's
+    # assignment at their returned centroids
     from paper_2204_07485_amd import bigmeans
     X = torch.from_numpy(synth.make_wide()).cuda()
     solves = synth.wide_solves()[:64]
@@ -154,11 +200,22 @@ def test_batched_wide_workload_sampled():
     assert info["rounds"] == int(passes.max())
     r0 = np.concatenate([[0], np.cumsum(s)])
     c0 = np.concatenate([[0], np.cumsum(k)])
-    for j in (0, 1, 2, 3):
+    for j in (0, 1, 2, 3, 5, 6):
         Pj = P[r0[j]:r0[j + 1]]
         Cj = C0[c0[j]:c0[j + 1]].clone()
         sdg, slab, sf, sp = bigmeans.kmeans_lloyd(Pj, Cj, deg[c0[j]:c0[j + 1]], **kw)
         assert_sse(f[j], sf)
         assert passes[j] == sp
-        same = (lab[r0[j]:r0[j + 1]] == slab).float().mean().item()
-        assert same > 0.9999
+        Pn = Pj.cpu().numpy()
+        Cb = C[c0[j]:c0[j + 1]].cpu().numpy()
+        dgj = dg[c0[j]:c0[j + 1]]
+        Cs = Cj.cpu().numpy()
+        assert_centroids(Cb, Cs, sdg)
+        # the same labels as the single-problem path, up to near ties
+        assert_labels(lab[r0[j]:r0[j + 1]].cpu().numpy(), slab.cpu().numpy(), Pn, Cs, sdg)
+        # at any size: the objective and labels are those the oracle gives
+        # the batched path's own centroids
+        with oracle.threaded():
+            olab, _, of = oracle.assign(Pn, Cb, dgj)
+        assert_sse(f[j], of)
+        assert_labels(lab[r0[j]:r0[j + 1]].cpu().numpy(), olab, Pn, Cb, dgj)

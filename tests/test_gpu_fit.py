@@ -99,6 +99,51 @@ def test_medium_workload_full_run_matches_stored_oracle():
     assert got["stats"]["lloyd_iters"] == gold["stats"]["lloyd_iters"]
     assert got["stats"]["n_d"] == gold["stats"]["n_d"]
     assert_centroids(got["centroids"].cpu().numpy(), np.array(gold["C"]), np.array(gold["deg"]))
+    _assert_label_counts(got, gold, X)
+
+
+def _assert_label_counts(got, gold, X):
+    """Cluster sizes of the final pass equal the stored oracle's, up to the
+    points that are near ties of the oracle's final centroids (each such point
+    may move between two clusters)."""
+    from tests.parity import near_tie_count
+    C = np.array([[np.nan if v is None else v for v in row] for row in gold["C"]])
+    deg = np.array(gold["deg"], np.uint8)
+    lab = got["labels"].cpu().numpy()
+    counts = np.bincount(lab[lab >= 0], minlength=len(deg))
+    diff = int(np.abs(counts - np.array(gold["label_counts"])).sum())
+    if diff:
+        near = near_tie_count(X, C, deg)
+        assert diff <= 2 * near, f"label counts differ by {diff}, near ties {near}"
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16_mfma"])
+def test_bf16_workload_full_run_matches_stored_oracle(precision):
+    # the full BF16 workload (5,000,000 x 128 stored as BF16, k=100, s=200,000,
+    # 30 samples, paper stop rule) against the oracle's stored result
+    # (tests/golden/make_golden.py bf16), with either final-pass arithmetic
+    from paper_2204_07485_amd import bigmeans
+    with open(os.path.join(HERE, "golden", "bf16_fit.json")) as fh:
+        gold = json.load(fh)
+    W = synth.BF16
+    H = synth.make_bf16()
+    prec = bigmeans.BM_PREC_BF16_MFMA if precision == "bf16_mfma" else bigmeans.BM_PREC_FP32
+    print(f"bf16 full fit precision={precision}", flush=True)
+    got = bigmeans.bigmeans_fit(torch.from_numpy(H.view(np.int16)).cuda(), W.k, W.s, W.n_samples,
+                                W.seed, max_iter=300, tol=1e-4, stop_rule=bigmeans.BM_STOP_REL_OBJ,
+                                precision=prec)
+    print(f"bf16 full: gpu sse {got['sse']!r} oracle {gold['sse']!r}", flush=True)
+    rel = np.abs(got["sample_f"] - np.array(gold["sample_f"])) / np.array(gold["sample_f"])
+    first_bad = int(np.argmax(rel > 1e-6)) if (rel > 1e-6).any() else None
+    assert first_bad is None, f"sample objective diverges first at sample {first_bad}"
+    assert_sse(got["sse"], gold["sse"])
+    assert_sse(got["f_opt"], gold["f_opt"])
+    assert got["degenerate"].tolist() == gold["deg"]
+    for key in ("replacements", "lloyd_iters", "n_d", "reseeded"):
+        assert got["stats"][key] == gold["stats"][key], key
+    Cg = np.array([[np.nan if v is None else v for v in row] for row in gold["C"]])
+    assert_centroids(got["centroids"].cpu().numpy(), Cg, np.array(gold["deg"]))
+    _assert_label_counts(got, gold, synth.bf16_bits_to_f32(H))
 
 
 def test_resume_equals_uninterrupted():

@@ -81,6 +81,28 @@ def lockstep(P, C0, deg0, steps):
     return min_gap
 
 
+# Cases whose oracle trajectory comes within the near-tie band (smallest
+# relative top-2 gap below 1e-5 within the first 60 steps; computed from the
+# oracle alone, so fixed by the inputs).  Only these may take the relaxed
+# whole-run check, and only when the strict one fails.
+NEAR_TIE_CASES = {(40_000, 16, 25, 1, 0), (40_000, 16, 25, 0, 0), (9_999, 3, 7, 1, 13),
+                  (30_000, 68, 50, 1, 0), (5_000, 128, 20, 1, 0)}
+
+
+def _strict_equal(g, r, P):
+    gC, gdeg, glab, gf, gp = g
+    rC, rdeg, rlab, rf, rp = r
+    try:
+        assert_labels(glab, rlab, P, rC, rdeg)
+        assert gp == rp
+        assert np.array_equal(gdeg, rdeg)
+        assert_sse(gf, rf)
+        assert_centroids(gC, rC, rdeg, P, rlab)
+        return True
+    except AssertionError:
+        return False
+
+
 @pytest.mark.parametrize("s,d,k,rule,grid", [(2000, 8, 10, 0, 0), (40_000, 16, 25, 1, 0),
                                              (40_000, 16, 25, 0, 0), (9_999, 3, 7, 1, 13),
                                              (30_000, 68, 50, 1, 0), (5_000, 128, 20, 1, 0),
@@ -96,6 +118,8 @@ def test_lloyd_matches_oracle(s, d, k, rule, grid):
                                          grid=grid)
     rC, rdeg, rlab, rf, rp, _ = oracle.lloyd(P, C0, deg, max_iter=max_iter, tol=1e-4, stop_rule=rule)
     min_gap = lockstep(P, C0, deg, steps=min(rp, 60))
+    case = (s, d, k, rule, grid)
+    assert (min_gap < LABEL_TIE_REL) == (case in NEAR_TIE_CASES), f"near-tie status of {case}"
     if min_gap >= LABEL_TIE_REL:
         # no near tie on the oracle's path: the whole run must agree
         assert_labels(glab, rlab, P, rC, rdeg)
@@ -103,9 +127,12 @@ def test_lloyd_matches_oracle(s, d, k, rule, grid):
         assert np.array_equal(gdeg, rdeg)
         assert_sse(gf, rf)
         assert_centroids(gC, rC, rdeg, P, rlab)
-    else:
-        print(f"  oracle path meets a near tie (gap {min_gap:.2e}); whole-run check relaxed",
+    elif _strict_equal((gC, gdeg, glab, gf, gp), (rC, rdeg, rlab, rf, rp), P):
+        print(f"  near tie on the oracle path (gap {min_gap:.2e}); whole run still equal",
               flush=True)
+    else:
+        print(f"  near tie on the oracle path (gap {min_gap:.2e}); trajectories diverged "
+              f"(passes {gp} vs {rp}, f {gf!r} vs {rf!r})", flush=True)
         # the GPU's own result is self-consistent: its objective is that of its
         # centroids, its labels are their nearest centroids, and it is a local
         # optimum of comparable quality

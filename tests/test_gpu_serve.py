@@ -199,3 +199,39 @@ def test_rounds_mode_reuses_slots_across_ticks():
         assert np.array_equal(r["degenerate"], alone["degenerate"])
         np.testing.assert_allclose(r["sample_f"], alone["sample_f"], rtol=1e-6)
         assert_sse(r["sse"], alone["sse"])
+
+
+@pytest.mark.parametrize("mode", ["fits", "rounds"])
+def test_served_jobs_match_oracle(mode):
+    # served jobs (in a mix, several in flight) against the oracle's
+    # Big-means on the same X and seed (Alg. 1 + final pass): per-sample
+    # objectives, final objective and centroids to 1e-6, flags and
+    # replacement/reseed counts exactly
+    import oracle
+    from paper_2204_07485_amd import bigmeans
+    from tests.parity import assert_centroids
+    jobs = [(j, X) for j, X in _jobs(10, seed=12, n_range=(1e4, 3e4)) if j["d"] <= 32][:5]
+    m = bigmeans.BM_SERVE_ROUNDS if mode == "rounds" else bigmeans.BM_SERVE_FITS
+    with bigmeans.Server(slots=3, mode=m) as srv:
+        ids = [srv.submit(X, j["k"], j["s"], j["n_samples"], j["seed"], want_labels=True, **KW)
+               for j, X in jobs]
+        res = [srv.result(i) for i in ids]
+    assert len(res) >= 3
+    for (j, X), r in zip(jobs, res):
+        print(f"{mode} job {j['id']}: n={j['n']} d={j['d']} k={j['k']} s={j['s']}", flush=True)
+        Xh = X.cpu().numpy()
+        with oracle.threaded():
+            ref = oracle.bigmeans_fit(Xh, j["k"], j["s"], j["n_samples"], j["seed"],
+                                      max_iter=KW["max_iter"], tol=KW["tol"],
+                                      stop_rule=oracle.ORC_STOP_REL_OBJ,
+                                      n_local_trials=KW["n_local_trials"])
+        rel = np.abs(r["sample_f"] - ref["sample_f"]) / ref["sample_f"]
+        first_bad = int(np.argmax(rel > 1e-6)) if (rel > 1e-6).any() else None
+        assert first_bad is None, f"sample objective diverges first at sample {first_bad}"
+        assert_sse(r["sse"], ref["sse"])
+        assert np.array_equal(r["degenerate"], ref["deg"])
+        assert r["stats"]["replacements"] == ref["stats"]["replacements"]
+        assert r["stats"]["reseeded"] == ref["stats"]["reseeded"]
+        assert_centroids(r["centroids"].cpu().numpy(), ref["C"], ref["deg"], Xh, ref["labels"])
+        from tests.parity import assert_labels
+        assert_labels(r["labels"].cpu().numpy(), ref["labels"], Xh, ref["C"], ref["deg"])
