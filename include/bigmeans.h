@@ -179,6 +179,25 @@ bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, con
                         double* sse);
 
 /*
+ * kmeans_assign_noalloc -- kmeans_assign for callers that cannot allocate
+ * device memory (code running under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * kmeans_assign (labels and objective identical); it calls no hipMalloc,
+ * hipFree or allocating library routine.  Its scratch (the flags, one FP64
+ * partial per workgroup, a counter and the objective) is a fixed 64 KiB
+ * array in device memory that every GPU the library runs on holds until the
+ * process ends; calls whose scratch would exceed it (k plus the workgroup
+ * count of the call: about 7,000 workgroup partials with k <= 8,000) return
+ * BM_EINVAL.  Calls on one GPU share that array: the library serialises them
+ * within the process (each returns after its work is done); work from such
+ * calls that a caller captures and replays concurrently with another call
+ * would race.
+ */
+bm_status kmeans_assign_noalloc(const void* X, int64_t n, int32_t d, const float* C,
+                                const uint8_t* deg, int32_t k, const bm_options* opt,
+                                int32_t* labels, float* min_d2, double* sse);
+
+/*
  * kmeanspp_seed -- K-means++ (Sec. 2, greedy form of Sec. 5) applied to the
  * degenerate slots of C, as in the reseeding step of Alg. 1 (Sec. 3.3).
  *   P          device s x d FP32: the points to seed from (a sample).

@@ -27,7 +27,8 @@ FUNCTIONS = ["bm_default_options", "bm_last_error", "bm_release_scratch", "bm_ab
              "bigmeans_fit", "kmeans_assign", "kmeanspp_seed", "kmeans_lloyd",
              "bm_sample_indices", "bm_gather_rows", "kmeans_lloyd_batched",
              "bm_serve_default_config", "bm_ctx_create", "bm_ctx_submit", "bm_ctx_poll",
-             "bm_ctx_wait", "bm_ctx_cancel", "bm_ctx_release", "bm_ctx_info", "bm_ctx_destroy"]
+             "bm_ctx_wait", "bm_ctx_cancel", "bm_ctx_release", "bm_ctx_info", "bm_ctx_destroy",
+             "kmeans_assign_noalloc"]
 
 
 class BigmeansError(RuntimeError):
@@ -117,6 +118,8 @@ def load(path=LIB_PATH):
     L.bigmeans_fit.restype = I32
     L.kmeans_assign.argtypes = [P, I64, I32, P, P, I32, P, P, P, P]
     L.kmeans_assign.restype = I32
+    L.kmeans_assign_noalloc.argtypes = [P, I64, I32, P, P, I32, P, P, P, P]
+    L.kmeans_assign_noalloc.restype = I32
     L.kmeanspp_seed.argtypes = [P, I64, I32, I32, P, P, U64, U64, P]
     L.kmeanspp_seed.restype = I32
     L.kmeans_lloyd.argtypes = [P, I64, I32, I32, P, P, P, P, P, P]
@@ -238,6 +241,16 @@ def bigmeans_fit(X, k, s, n_samples, seed, want_labels=True, want_sse=True, stat
 
 
 def kmeans_assign(X, C, deg=None, want_labels=True, want_min_d2=False, **opts):
+    return _assign("kmeans_assign", X, C, deg, want_labels, want_min_d2, opts)
+
+
+def kmeans_assign_noalloc(X, C, deg=None, want_labels=True, want_min_d2=False, **opts):
+    """kmeans_assign through the entry point whose scratch is a fixed device
+    array (no device allocation by the library)."""
+    return _assign("kmeans_assign_noalloc", X, C, deg, want_labels, want_min_d2, opts)
+
+
+def _assign(entry, X, C, deg, want_labels, want_min_d2, opts):
     L = load()
     n, d = X.shape
     k = C.shape[0]
@@ -248,9 +261,9 @@ def kmeans_assign(X, C, deg=None, want_labels=True, want_min_d2=False, **opts):
     labels = torch.empty(n, dtype=torch.int32, device=X.device) if want_labels else None
     mind = torch.empty(n, dtype=torch.float32, device=X.device) if want_min_d2 else None
     sse = ct.c_double(0.0)
-    rc = L.kmeans_assign(xp, n, d, cp, None if dg is None else dg.ctypes.data_as(ct.c_void_p), k,
-                         ct.byref(o), None if labels is None else ct.c_void_p(labels.data_ptr()),
-                         None if mind is None else ct.c_void_p(mind.data_ptr()), ct.byref(sse))
+    rc = getattr(L, entry)(xp, n, d, cp, None if dg is None else dg.ctypes.data_as(ct.c_void_p), k,
+                           ct.byref(o), None if labels is None else ct.c_void_p(labels.data_ptr()),
+                           None if mind is None else ct.c_void_p(mind.data_ptr()), ct.byref(sse))
     _check(rc)
     return labels, mind, sse.value
 

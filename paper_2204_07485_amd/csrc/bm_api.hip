@@ -165,6 +165,8 @@ static bm_status resolve(const bm_options* in, bm_options* out) {
   return BM_OK;
 }
 
+bm_status resolve_options(const bm_options* in, bm_options* out) { return resolve(in, out); }
+
 // ---------------------------------------------------------------------------
 // solver configuration shared by the entry points that run the solver
 

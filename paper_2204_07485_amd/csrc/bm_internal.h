@@ -138,6 +138,9 @@ bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int
                   int32_t* labels, uint8_t* degenerate, bm_stats* stats, int grid_cap);
 bm_status solver_coresident_blocks(int d, int k, int64_t s, int64_t n, int* blocks);
 
+// Options with defaults filled in and validated (bm_api.hip).
+bm_status resolve_options(const bm_options* in, bm_options* out);
+
 // Error reporting for the ABI layer.
 bm_status set_error(bm_status code, const char* fmt, ...);
 void clear_error();
