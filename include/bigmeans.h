@@ -58,8 +58,10 @@ enum { BM_F32 = 0, BM_BF16 = 1 };               /* element type of X       */
 enum { BM_STOP_SHIFT = 0, BM_STOP_REL_OBJ = 1 }; /* Lloyd stop rule         */
 enum { BM_CMP_FOPT = 0, BM_CMP_RESAMPLE = 1 };   /* keep-the-best reference */
 enum { BM_PREC_FP32 = 0, BM_PREC_BF16_MFMA = 1 }; /* distance arithmetic    */
+enum { BM_INIT_KMEANSPP = 0, BM_INIT_FORGY = 1 };  /* (re)initialisation     */
+enum { BM_FINAL_ASSIGN = 0, BM_FINAL_POLISH = 1 }; /* last step of a fit     */
 
-#define BM_ABI_VERSION 1
+#define BM_ABI_VERSION 2
 
 /* Options.  Fill with bm_default_options(); fields are read only when
  * struct_size covers them, so callers built against an older header keep
@@ -96,6 +98,25 @@ typedef struct bm_options {
                           /* a wait that exceeds it aborts the call (BM_EDEVICE)  */
   int32_t* sample_idx;    /* optional device out, n_samples x s sampled indices   */
   double* sample_f;       /* optional host out, n_samples objectives f(C'',P)     */
+  /* --- ABI version 2 --- */
+  int32_t init_method;    /* how degenerate centroids are (re)initialised on a    */
+                          /* sample (Sec. 3.3 allows other strategies):           */
+                          /* BM_INIT_KMEANSPP (default; Sec. 2, greedy with       */
+                          /* n_local_trials candidates, Sec. 5) or BM_INIT_FORGY  */
+                          /* (each takes a uniformly drawn sample row, draws from */
+                          /* the K-means++ stream, independent per slot)          */
+  int32_t final_mode;     /* bigmeans_fit's last step: BM_FINAL_ASSIGN (default,  */
+                          /* Alg. 1: assign every point to the incumbent) or      */
+                          /* BM_FINAL_POLISH (Sec. 3.4: K-means on all of X from  */
+                          /* the incumbent, with this struct's stop rule,         */
+                          /* tolerance and cap; then labels and sse belong to the */
+                          /* polished centroids; FP32 X only, else BM_ENOTSUP)    */
+  double time_budget_ms;  /* > 0: the stop condition of Sec. 5 -- the sample loop */
+                          /* stops before the first sample that starts after this */
+                          /* much device time (sample 0 always runs); n_samples   */
+                          /* is then a cap; stats->samples tells how many ran.    */
+                          /* Processing s samples gives exactly the result of a   */
+                          /* run with n_samples = s.  0 (default): no budget      */
 } bm_options;
 
 /* Per-call counters (all optional; pass NULL). */
@@ -120,6 +141,9 @@ typedef struct bm_stats {
   double ms_lloyd_wait;   /* ... of which waiting in the assignment-pass barrier  */
   int64_t rechecked;      /* final pass, BM_PREC_BF16_MFMA: points recomputed on  */
                           /* the FP32 path (near-ties)                            */
+  /* --- ABI version 2 --- */
+  int32_t final_passes;   /* BM_FINAL_POLISH: assignment passes over all of X     */
+  int32_t pad_;
 } bm_stats;
 
 /* Fill *opt with defaults (struct_size set).  Returns BM_EINVAL on NULL. */
@@ -161,6 +185,56 @@ bm_status bigmeans_fit(const void* X, int64_t n, int32_t d, int32_t k, int64_t s
                        int32_t n_samples, uint64_t seed, const bm_options* opt,
                        float* centroids, double* sse, int32_t* labels, uint8_t* degenerate,
                        bm_stats* stats);
+
+/*
+ * bigmeans_fit_collective -- the collective parallel form of Big-means
+ * (Sec. 3.6, third scheme) on one GPU: n_rounds rounds of n_workers workers.
+ * Worker w of round r clusters its own sample, index t = r * n_workers + w of
+ * the random stream, starting from the incumbent of the previous rounds (all
+ * degenerate in round 0): it reinitialises the incumbent's degenerate
+ * centroids on its sample (opt->init_method) and runs K-means there.  All
+ * workers of a round run their K-means together in the batched kernels
+ * (kmeans_lloyd_batched).  After the round the worker with the smallest
+ * sample objective (ties to the lowest w) replaces the incumbent if that
+ * objective is below f_opt (Alg. 1's keep-the-best).  Then the final
+ * assignment (Alg. 1 last step).  With n_workers = 1 this is bigmeans_fit.
+ *   X, n, d, k, s, seed, centroids, sse, labels, degenerate, stats: as for
+ *               bigmeans_fit (stats->samples = rounds x workers; the
+ *               per-phase times are not filled).
+ *   n_workers   1..1024; n_rounds >= 1; n_rounds x n_workers < 2^32.
+ *   opt         as for bigmeans_fit, except that compare_rule must be
+ *               BM_CMP_FOPT, and resume, t_start, time_budget_ms,
+ *               final_mode, sample_idx and sample_f are not used.
+ *   worker_f    host, n_rounds x n_workers out: every worker's f(C'', P), or NULL.
+ * Errors: as bigmeans_fit; BM_ENOTSUP for compare_rule BM_CMP_RESAMPLE.
+ */
+bm_status bigmeans_fit_collective(const void* X, int64_t n, int32_t d, int32_t k, int64_t s,
+                                  int32_t n_workers, int32_t n_rounds, uint64_t seed,
+                                  const bm_options* opt, float* centroids, double* sse,
+                                  int32_t* labels, uint8_t* degenerate, bm_stats* stats,
+                                  double* worker_f);
+
+/*
+ * bigmeans_sample_size_sweep -- the rule of thumb of Sec. 5 for choosing s:
+ * run bigmeans_fit with s = s_min, 2 s_min, 4 s_min, ... (capped at s_max and
+ * n) while the final objective on X keeps decreasing; stop at the first size
+ * that does not improve on the best so far (or at the cap), and return the
+ * best size's fit.
+ *   s_min, s_max  k <= s_min <= s_max.
+ *   n_samples, seed, opt  as for bigmeans_fit, for every run (final_mode must
+ *               be BM_FINAL_ASSIGN; resume is not used).
+ *   centroids, degenerate, sse, labels  the best run's outputs (device k x d,
+ *               host k, host, device n or NULL); sse is required.
+ *   s_best      host out: the best sample size.
+ *   s_tried, sse_tried  host out, the sizes run and their objectives, up to
+ *               max_tried entries (either may be NULL); n_tried host out.
+ */
+bm_status bigmeans_sample_size_sweep(const void* X, int64_t n, int32_t d, int32_t k,
+                                     int64_t s_min, int64_t s_max, int32_t n_samples,
+                                     uint64_t seed, const bm_options* opt, float* centroids,
+                                     double* sse, int32_t* labels, uint8_t* degenerate,
+                                     int64_t* s_best, int64_t* s_tried, double* sse_tried,
+                                     int32_t max_tried, int32_t* n_tried);
 
 /*
  * kmeans_assign -- assignment step (Sec. 2) and objective, Eq. (1): every row

@@ -22,13 +22,15 @@ BM_F32, BM_BF16 = 0, 1
 BM_STOP_SHIFT, BM_STOP_REL_OBJ = 0, 1
 BM_CMP_FOPT, BM_CMP_RESAMPLE = 0, 1
 BM_PREC_FP32, BM_PREC_BF16_MFMA = 0, 1
+BM_INIT_KMEANSPP, BM_INIT_FORGY = 0, 1
+BM_FINAL_ASSIGN, BM_FINAL_POLISH = 0, 1
 
 FUNCTIONS = ["bm_default_options", "bm_last_error", "bm_release_scratch", "bm_abi_version",
              "bigmeans_fit", "kmeans_assign", "kmeanspp_seed", "kmeans_lloyd",
              "bm_sample_indices", "bm_gather_rows", "kmeans_lloyd_batched",
              "bm_serve_default_config", "bm_ctx_create", "bm_ctx_submit", "bm_ctx_poll",
              "bm_ctx_wait", "bm_ctx_cancel", "bm_ctx_release", "bm_ctx_info", "bm_ctx_destroy",
-             "kmeans_assign_noalloc"]
+             "kmeans_assign_noalloc", "bigmeans_fit_collective", "bigmeans_sample_size_sweep"]
 
 
 class BigmeansError(RuntimeError):
@@ -45,7 +47,8 @@ class Options(ct.Structure):
                 ("stream", ct.c_void_p), ("grid", ct.c_int32), ("t_start", ct.c_int32),
                 ("resume", ct.c_int32), ("f_opt_in", ct.c_double),
                 ("spin_limit", ct.c_uint32), ("sample_idx", ct.c_void_p),
-                ("sample_f", ct.c_void_p)]
+                ("sample_f", ct.c_void_p), ("init_method", ct.c_int32),
+                ("final_mode", ct.c_int32), ("time_budget_ms", ct.c_double)]
 
 
 class Stats(ct.Structure):
@@ -57,10 +60,10 @@ class Stats(ct.Structure):
                 ("ms_sampling", ct.c_double), ("ms_seeding", ct.c_double),
                 ("ms_lloyd", ct.c_double), ("ms_lloyd_pass", ct.c_double),
                 ("ms_lloyd_post", ct.c_double), ("ms_lloyd_wait", ct.c_double),
-                ("rechecked", ct.c_int64)]
+                ("rechecked", ct.c_int64), ("final_passes", ct.c_int32), ("pad_", ct.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f not in ("struct_size", "pad_")}
 
 
 class ServeConfig(ct.Structure):
@@ -120,6 +123,11 @@ def load(path=LIB_PATH):
     L.kmeans_assign.restype = I32
     L.kmeans_assign_noalloc.argtypes = [P, I64, I32, P, P, I32, P, P, P, P]
     L.kmeans_assign_noalloc.restype = I32
+    L.bigmeans_fit_collective.argtypes = [P, I64, I32, I32, I64, I32, I32, U64, P, P, P, P, P, P, P]
+    L.bigmeans_fit_collective.restype = I32
+    L.bigmeans_sample_size_sweep.argtypes = [P, I64, I32, I32, I64, I64, I32, U64, P, P, P, P, P, P,
+                                             P, P, I32, P]
+    L.bigmeans_sample_size_sweep.restype = I32
     L.kmeanspp_seed.argtypes = [P, I64, I32, I32, P, P, U64, U64, P]
     L.kmeanspp_seed.restype = I32
     L.kmeans_lloyd.argtypes = [P, I64, I32, I32, P, P, P, P, P, P]
@@ -238,6 +246,57 @@ def bigmeans_fit(X, k, s, n_samples, seed, want_labels=True, want_sse=True, stat
     return {"centroids": cent, "degenerate": deg, "sse": sse.value if want_sse else None,
             "labels": labels, "f_opt": st.f_opt, "sample_f": sf, "sample_idx": sidx,
             "stats": st.as_dict()}
+
+
+def bigmeans_fit_collective(X, k, s, n_workers, n_rounds, seed, want_labels=True, **opts):
+    """Collective parallel Big-means (bigmeans_fit_collective).  Returns a dict:
+    centroids, degenerate, sse, labels, f_opt, worker_f (rounds x workers), stats."""
+    L = load()
+    n, d = X.shape
+    xp, xdt = _x_ptr(X)
+    o = options(x_dtype=xdt, **opts)
+    cent = torch.empty((k, d), dtype=torch.float32, device=X.device)
+    deg = np.ones(k, dtype=np.uint8)
+    labels = torch.empty(n, dtype=torch.int32, device=X.device) if want_labels else None
+    wf = np.zeros((n_rounds, n_workers), dtype=np.float64)
+    sse = ct.c_double(0.0)
+    st = Stats()
+    st.struct_size = ct.sizeof(Stats)
+    rc = L.bigmeans_fit_collective(xp, n, d, k, s, n_workers, n_rounds, ct.c_uint64(seed),
+                                   ct.byref(o), ct.c_void_p(cent.data_ptr()), ct.byref(sse),
+                                   ct.c_void_p(labels.data_ptr()) if labels is not None else None,
+                                   deg.ctypes.data_as(ct.c_void_p), ct.byref(st),
+                                   wf.ctypes.data_as(ct.c_void_p))
+    _check(rc)
+    return {"centroids": cent, "degenerate": deg, "sse": sse.value, "labels": labels,
+            "f_opt": st.f_opt, "worker_f": wf, "stats": st.as_dict()}
+
+
+def sample_size_sweep(X, k, s_min, s_max, n_samples, seed, want_labels=False, **opts):
+    """The sample-size rule of thumb (bigmeans_sample_size_sweep).  Returns a
+    dict: s_best, sse, centroids, degenerate, labels, tried [(s, sse), ...]."""
+    L = load()
+    n, d = X.shape
+    xp, xdt = _x_ptr(X)
+    o = options(x_dtype=xdt, **opts)
+    cent = torch.empty((k, d), dtype=torch.float32, device=X.device)
+    deg = np.ones(k, dtype=np.uint8)
+    labels = torch.empty(n, dtype=torch.int32, device=X.device) if want_labels else None
+    sse = ct.c_double(0.0)
+    s_best = ct.c_int64(0)
+    s_tried = np.zeros(64, dtype=np.int64)
+    sse_tried = np.zeros(64, dtype=np.float64)
+    m = ct.c_int32(0)
+    rc = L.bigmeans_sample_size_sweep(xp, n, d, k, s_min, s_max, n_samples, ct.c_uint64(seed),
+                                      ct.byref(o), ct.c_void_p(cent.data_ptr()), ct.byref(sse),
+                                      ct.c_void_p(labels.data_ptr()) if labels is not None else None,
+                                      deg.ctypes.data_as(ct.c_void_p), ct.byref(s_best),
+                                      s_tried.ctypes.data_as(ct.c_void_p),
+                                      sse_tried.ctypes.data_as(ct.c_void_p), 64, ct.byref(m))
+    _check(rc)
+    return {"s_best": s_best.value, "sse": sse.value, "centroids": cent, "degenerate": deg,
+            "labels": labels,
+            "tried": [(int(s_tried[i]), float(sse_tried[i])) for i in range(m.value)]}
 
 
 def kmeans_assign(X, C, deg=None, want_labels=True, want_min_d2=False, **opts):
@@ -499,3 +558,19 @@ def last_assign_ms():
 
 def release_scratch():
     _check(load().bm_release_scratch())
+
+
+def debug_counters():
+    """Raw device counters of this thread's last bigmeans_fit (bm_debug_counters):
+    a dict of the per-phase clock ticks and event counts."""
+    L = load()
+    out = (ct.c_int64 * 24)()
+    L.bm_debug_counters.argtypes = [ct.c_void_p, ct.c_int32]
+    L.bm_debug_counters.restype = ct.c_int32
+    _check(L.bm_debug_counters(out, 24))
+    names = {0: "passes", 1: "reseeded", 2: "replaced", 3: "n_d", 4: "boundary", 5: "samples",
+             6: "select_passes", 8: "ticks_sample", 9: "ticks_seed", 10: "ticks_lloyd",
+             11: "ticks_pass", 12: "ticks_post", 13: "ticks_barrier", 14: "ticks_collect",
+             15: "ticks_collect_wait", 16: "ticks_select", 17: "ticks_emit", 18: "ticks_assign",
+             19: "ticks_flush"}
+    return {v: int(out[k]) for k, v in names.items()}

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -50,6 +51,10 @@ void clear_error() { g_err[0] = '\0'; }
 static std::mutex g_mu;
 static std::mutex g_launch_mu;
 static ScratchPool g_pool[64];
+// The batched Lloyd's scratch when it runs inside a call that keeps its own
+// buffers in g_pool (the full-data polish, the collective mode), under g_mu.
+static ScratchPool g_pool_inner[64];
+static thread_local bool t_inner = false;
 // A serving slot's worker thread uses its own pool (no shared state, no lock).
 static thread_local ScratchPool* t_pool = nullptr;
 
@@ -79,7 +84,7 @@ void* scratch_get(size_t bytes, hipStream_t stream, bm_status* st) {
     *st = set_error(BM_EDEVICE, "no current HIP device");
     return nullptr;
   }
-  ScratchPool& p = t_pool ? *t_pool : g_pool[dev];
+  ScratchPool& p = t_inner ? g_pool_inner[dev] : (t_pool ? *t_pool : g_pool[dev]);
   if (p.bytes >= bytes) {
     *st = BM_OK;
     return p.ptr;
@@ -103,12 +108,22 @@ void* scratch_get(size_t bytes, hipStream_t stream, bm_status* st) {
 }
 
 void scratch_release() {
-  for (auto& p : g_pool) {
-    if (p.ptr) (void)hipFree(p.ptr);
-    p.ptr = nullptr;
-    p.bytes = 0;
+  for (ScratchPool* pools : {g_pool, g_pool_inner}) {
+    for (int i = 0; i < 64; ++i) {
+      ScratchPool& p = pools[i];
+      if (p.ptr) (void)hipFree(p.ptr);
+      p.ptr = nullptr;
+      p.bytes = 0;
+    }
   }
 }
+
+// While alive, scratch_get() on this thread hands out the inner pool.
+struct InnerScratch {
+  bool prev;
+  InnerScratch() : prev(t_inner) { t_inner = true; }
+  ~InnerScratch() { t_inner = prev; }
+};
 
 // Bump layout over the scratch block: first pass sizes, second pass binds.
 struct Layout {
@@ -162,6 +177,12 @@ static bm_status resolve(const bm_options* in, bm_options* out) {
     return set_error(BM_EINVAL, "BM_PREC_BF16_MFMA needs BF16 points (x_dtype = BM_BF16)");
   if (out->grid < 0 || out->grid > kMaxGrid) return set_error(BM_EINVAL, "grid %d", out->grid);
   if (out->t_start < 0) return set_error(BM_EINVAL, "t_start must be >= 0");
+  if (out->init_method != BM_INIT_KMEANSPP && out->init_method != BM_INIT_FORGY)
+    return set_error(BM_EINVAL, "init_method %d", out->init_method);
+  if (out->final_mode != BM_FINAL_ASSIGN && out->final_mode != BM_FINAL_POLISH)
+    return set_error(BM_EINVAL, "final_mode %d", out->final_mode);
+  if (!(out->time_budget_ms >= 0.0) || out->time_budget_ms > 1e12)
+    return set_error(BM_EINVAL, "time_budget_ms must be in [0, 1e12]");
   return BM_OK;
 }
 
@@ -244,6 +265,7 @@ static void layout_solver(char* base, int64_t n, int64_t s, int d, int k, int T,
   a.bar = L.take<GridBarrier>(1);
   a.err = L.take<int32_t>(1);
   a.presample_miss = L.take<int32_t>(1);
+  a.stop_flag = L.take<int32_t>(1);
   a.counters = L.take<int64_t>(kNumCounters);
   a.cand_count = L.take<uint32_t>(B);
   a.hist = L.take<uint32_t>(3 * 256);
@@ -364,6 +386,219 @@ static int build_tiles(const std::vector<int64_t>& s, int tile_rows, std::vector
   return static_cast<int>(tile_solve->size());
 }
 
+// kmeans_lloyd_batched after option resolution; the caller holds g_mu.
+static bm_status batched_run(int32_t n_solves, const float* P, int32_t d, const int64_t* s,
+                             const int32_t* k, float* C, uint8_t* deg, const bm_options& o,
+                             int32_t* labels, double* f, int32_t* passes) {
+  bm_status st = BM_OK;
+  if (n_solves < 1 || d < 1) return set_error(BM_EINVAL, "need n_solves >= 1 and d >= 1");
+  if (!P || !s || !k || !C || !deg) return set_error(BM_EINVAL, "P, s, k, C and deg are required");
+  if (padded_dim(d) < 0) return set_error(BM_ENOTSUP, "d = %d exceeds the limit of 256", d);
+  std::vector<int64_t> sv_s(n_solves);
+  std::vector<BatchSolve> hs(n_solves);
+  int64_t rows = 0, ktot = 0;
+  int kmax = 0;
+  for (int j = 0; j < n_solves; ++j) {
+    if (s[j] < 1 || k[j] < 1 || k[j] > s[j])
+      return set_error(BM_EINVAL, "solve %d: need 1 <= k <= s (s=%lld, k=%d)", j, (long long)s[j], k[j]);
+    int active = 0;
+    for (int q = 0; q < k[j]; ++q) active += deg[ktot + q] ? 0 : 1;
+    if (!active) return set_error(BM_EINVAL, "solve %d: every centroid is degenerate", j);
+    sv_s[j] = s[j];
+    memset(&hs[j], 0, sizeof(BatchSolve));
+    hs[j].row0 = rows;
+    hs[j].s = s[j];
+    hs[j].c0 = static_cast<int32_t>(ktot);
+    hs[j].k = k[j];
+    hs[j].status = kSolveRunning;
+    hs[j].iter = 1;
+    hs[j].f_prev = __builtin_inf();
+    rows += s[j];
+    ktot += k[j];
+    kmax = k[j] > kmax ? k[j] : kmax;
+    if (rows > 2147483647LL || ktot > 2147483647LL)
+      return set_error(BM_EINVAL, "more than 2^31 rows or centroids in the batch");
+  }
+  size_t lds_max = 0;
+  if ((st = max_lds_per_block(&lds_max)) != BM_OK) return st;
+  const bool sums_lds = batch_assign_lds(d, kmax, true) + 1024 <= lds_max;
+  if (!sums_lds && batch_assign_lds(d, kmax, false) + 1024 > lds_max)
+    return set_error(BM_ENOTSUP, "k x d = %d x %d centroids do not fit in one workgroup's LDS", kmax, d);
+  hipStream_t user = static_cast<hipStream_t>(o.stream);
+  int grid = 0;
+  if ((st = batch_assign_grid(d, kmax, sums_lds, &grid)) != BM_OK) return st;
+
+  // scratch: solve states, work list (sized for the smallest tile), tile
+  // objectives, FP64 sums, counts, FP64 means, flags, running counter
+  constexpr int kMinTile = 256;
+  int64_t max_tiles = 0;
+  for (int j = 0; j < n_solves; ++j) max_tiles += (s[j] + kMinTile - 1) / kMinTile;
+  BatchSolve* sv_d = nullptr;
+  int32_t* tiles_d = nullptr;
+  double* tile_f = nullptr;
+  double* sums = nullptr;
+  int32_t* cnt = nullptr;
+  double* c64 = nullptr;
+  float* cpad = nullptr;
+  float* ppad = nullptr;
+  uint8_t* deg_d = nullptr;
+  int* running = nullptr;
+  char* base = nullptr;
+  for (int round = 0; round < 2; ++round) {
+    Layout L;
+    L.base = base;
+    sv_d = L.take<BatchSolve>(n_solves);
+    tiles_d = L.take<int32_t>(max_tiles);
+    tile_f = L.take<double>(max_tiles);
+    sums = L.take<double>(ktot * padded_dim(d));
+    cnt = L.take<int32_t>(ktot);
+    c64 = L.take<double>(ktot * d);
+    cpad = L.take<float>(ktot * padded_dim(d));
+    ppad = L.take<float>(padded_dim(d) == d ? 1 : rows * padded_dim(d));
+    deg_d = L.take<uint8_t>(ktot);
+    running = L.take<int>(1);
+    if (round == 0) {
+      base = static_cast<char*>(scratch_get(L.off + 256, user, &st));
+      if (!base) return st;
+    }
+  }
+  // an internal stream (capturable; default priority) ordered after the caller's
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (stream) (void)hipStreamDestroy(stream);
+  };
+  auto fail = [&](bm_status code) {
+    if (stream) (void)hipStreamSynchronize(stream);
+    cleanup();
+    return code;
+  };
+#define BM_HIPB(call)                                                                          \
+  do {                                                                                         \
+    const hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(set_error(BM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)));       \
+  } while (0)
+  BM_HIPB(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+  BM_HIPB(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+  BM_HIPB(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+  BM_HIPB(hipEventRecord(ev_in, user));
+  BM_HIPB(hipStreamWaitEvent(stream, ev_in, 0));
+  BM_HIPB(hipMemcpyAsync(deg_d, deg, static_cast<size_t>(ktot), hipMemcpyHostToDevice, stream));
+  BM_HIPB(hipMemsetAsync(sums, 0, sizeof(double) * ktot * padded_dim(d), stream));
+  BM_HIPB(hipMemsetAsync(cnt, 0, sizeof(int32_t) * ktot, stream));
+  if ((st = launch_batch_init(C, c64, cpad, ktot, d, stream)) != BM_OK) return fail(st);
+  // rows DM wide for guard-free loads (a copy only when d is not already DM)
+  const float* Pp = P;
+  if (padded_dim(d) != d) {
+    if ((st = launch_pad_rows(P, ppad, rows, d, stream)) != BM_OK) return fail(st);
+    Pp = ppad;
+  }
+
+  // rows per tile: tuned once per shape by timing a dry assignment pass
+  std::vector<int32_t> tile_solve, tile0, ntiles;
+  const BatchShape shape{d, kmax, n_solves, rows};
+  int tile_rows = 0;
+  auto it_cache = g_tile_cache.find(shape);
+  auto upload = [&](int tr) -> bm_status {
+    const int nt = build_tiles(sv_s, tr, &tile_solve, &tile0, &ntiles);
+    for (int j = 0; j < n_solves; ++j) {
+      hs[j].tile0 = tile0[j];
+      hs[j].ntiles = ntiles[j];
+    }
+    BM_HIP(hipMemcpyAsync(tiles_d, tile_solve.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, stream));
+    BM_HIP(hipMemcpyAsync(sv_d, hs.data(), sizeof(BatchSolve) * n_solves, hipMemcpyHostToDevice, stream));
+    BM_HIP(hipStreamSynchronize(stream));  // the host vectors are reused
+    return BM_OK;
+  };
+  if (it_cache != g_tile_cache.end()) {
+    tile_rows = it_cache->second;
+  } else if (rows < 65536) {
+    tile_rows = 512;
+  } else {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    BM_HIPB(hipEventCreate(&t0));
+    BM_HIPB(hipEventCreate(&t1));
+    float best = 0.f;
+    for (int tr : {256, 512, 1024, 2048, 4096}) {
+      bm_status su = upload(tr);
+      if (su != BM_OK) return fail(su);
+      const int nt = static_cast<int>(tile_solve.size());
+      float ms = 0.f;
+      for (int rep = 0; rep < 2 && su == BM_OK; ++rep) {  // first run warms caches
+        BM_HIPB(hipEventRecord(t0, stream));
+        su = launch_batch_assign(Pp, d, C, cpad, deg_d, sv_d, tiles_d, nt, tr, kmax, sums_lds, sums,
+                                 cnt, tile_f, nullptr, 1, grid, stream);
+        BM_HIPB(hipEventRecord(t1, stream));
+        BM_HIPB(hipEventSynchronize(t1));
+        BM_HIPB(hipEventElapsedTime(&ms, t0, t1));
+      }
+      if (su != BM_OK) return fail(su);
+      if (tile_rows == 0 || ms < best) {
+        best = ms;
+        tile_rows = tr;
+      }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    g_tile_cache[shape] = tile_rows;
+  }
+  if ((st = upload(tile_rows)) != BM_OK) return fail(st);
+  const int nt = static_cast<int>(tile_solve.size());
+
+  // one round = assignment + update, captured once and launched per round
+  BM_HIPB(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  bm_status cs = launch_batch_assign(Pp, d, C, cpad, deg_d, sv_d, tiles_d, nt, tile_rows, kmax,
+                                     sums_lds, sums, cnt, tile_f, labels, 0, grid, stream);
+  if (cs == BM_OK)
+    cs = launch_batch_update(sv_d, n_solves, tile_f, sums, cnt, C, cpad, c64, deg_d, d, o.max_iter,
+                             o.tol, o.stop_rule, running, stream);
+  const hipError_t ce = hipStreamEndCapture(stream, &graph);
+  if (cs != BM_OK) return fail(cs);
+  if (ce != hipSuccess)
+    return fail(set_error(BM_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce)));
+  BM_HIPB(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  int still = 1;
+  int rounds = 0;
+  hipEvent_t r0 = nullptr, r1 = nullptr;
+  BM_HIPB(hipEventCreate(&r0));
+  BM_HIPB(hipEventCreate(&r1));
+  g_last_batch_ms.clear();
+  for (; rounds <= o.max_iter && still; ++rounds) {
+    BM_HIPB(hipMemsetAsync(running, 0, sizeof(int), stream));
+    BM_HIPB(hipEventRecord(r0, stream));
+    BM_HIPB(hipGraphLaunch(exec, stream));
+    BM_HIPB(hipEventRecord(r1, stream));
+    BM_HIPB(hipMemcpyAsync(&still, running, sizeof(int), hipMemcpyDeviceToHost, stream));
+    BM_HIPB(hipStreamSynchronize(stream));
+    g_last_batch_ms.push_back(elapsed_ms(r0, r1));
+  }
+  (void)hipEventDestroy(r0);
+  (void)hipEventDestroy(r1);
+  if (still) return fail(set_error(BM_EDEVICE, "batched Lloyd did not finish in max_iter + 1 rounds"));
+  BM_HIPB(hipMemcpyAsync(hs.data(), sv_d, sizeof(BatchSolve) * n_solves, hipMemcpyDeviceToHost, stream));
+  BM_HIPB(hipMemcpyAsync(deg, deg_d, static_cast<size_t>(ktot), hipMemcpyDeviceToHost, stream));
+  BM_HIPB(hipEventRecord(ev_out, stream));
+  BM_HIPB(hipStreamWaitEvent(user, ev_out, 0));
+  BM_HIPB(hipStreamSynchronize(stream));
+#undef BM_HIPB
+  for (int j = 0; j < n_solves; ++j) {
+    if (hs[j].status != kSolveDone) return fail(set_error(BM_EDEVICE, "solve %d did not finish", j));
+    if (f) f[j] = hs[j].f;
+    if (passes) passes[j] = hs[j].passes;
+  }
+  g_last_batch_rounds = rounds;
+  g_last_batch_tile = tile_rows;
+  cleanup();
+  return BM_OK;
+}
+
 }  // namespace bm
 
 using namespace bm;
@@ -383,8 +618,7 @@ const char* bm_last_error(void) { return g_err; }
 
 int32_t bm_abi_version(void) { return BM_ABI_VERSION; }
 
-// Raw per-phase counters of the last bigmeans_fit on this thread (diagnostics;
-// not declared in the public header).
+// Diagnostics and test hooks, declared in include/bigmeans_debug.h.
 // Test hook: presampling mode (0 automatic, 1 never, 2 force a window miss);
 // returns the previous mode.
 int32_t bm_debug_presample(int32_t mode) {
@@ -392,6 +626,7 @@ int32_t bm_debug_presample(int32_t mode) {
   return g_presample_mode.exchange(mode);
 }
 
+// Raw per-phase counters of the last bigmeans_fit on this thread.
 int32_t bm_debug_counters(int64_t* out, int32_t n) {
   if (!out || n < 1) return BM_EINVAL;
   for (int i = 0; i < n && i < kNumCounters; ++i) out[i] = g_last_counters[i];
@@ -399,12 +634,11 @@ int32_t bm_debug_counters(int64_t* out, int32_t n) {
 }
 
 // Points the last BM_PREC_BF16_MFMA kmeans_assign on this thread recomputed
-// on the FP32 path (diagnostics; not declared in the public header).
+// on the FP32 path.
 int64_t bm_debug_rechecked(void) { return g_last_rechecked; }
 
 // Device time (HIP events on the call's stream) of the assignment kernel of
-// the last kmeans_assign on this thread, in ms (diagnostics; not declared in
-// the public header).
+// the last kmeans_assign on this thread, in ms.
 double bm_debug_assign_ms(void) { return g_last_assign_ms; }
 
 bm_status bm_release_scratch(void) {
@@ -431,6 +665,8 @@ bm_status fit_validate(const void* X, int64_t n, int32_t d, int32_t k, int64_t s
     return set_error(BM_EINVAL, "sample indices exceed 2^32");
   if (stats && stats->struct_size != sizeof(bm_stats))
     return set_error(BM_EINVAL, "bm_stats.struct_size mismatch");
+  if (o->final_mode == BM_FINAL_POLISH && o->x_dtype != BM_F32)
+    return set_error(BM_ENOTSUP, "BM_FINAL_POLISH needs FP32 points");
   return BM_OK;
 }
 
@@ -472,14 +708,29 @@ bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int
       (st = plan_solver(d, k, s, n, grid_cap, &sp)) != BM_OK)
     return st;
 
-  const bool final_pass = sse || labels;
+  const bool polish = o.final_mode == BM_FINAL_POLISH && (sse || labels);
+  const bool final_pass = (sse || labels) && !polish;
   const bool final_mfma = final_pass && o.precision == BM_PREC_BF16_MFMA;
   int final_grid = final_pass ? assign_grid(n) : 0;
   if (final_mfma && (st = plan_assign_mfma(X, n, d, k, &final_grid)) != BM_OK) return st;
+  // with a time budget the samples are drawn a few at a time (most of a
+  // larger batch could go unused)
+  const bool budget = o.time_budget_ms > 0.0;
+  int sbatch = sample_slots(n, s, d, n_samples, sp.cand_cap);
+  if (budget && sbatch > 2) sbatch = 2;
+  uint64_t budget_ticks = 0;
+  if (budget) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+      return set_error(BM_EDEVICE, "cannot read the device wall-clock rate");
+    const double ticks = o.time_budget_ms * static_cast<double>(khz);
+    budget_ticks = ticks < 1.0 ? 1 : static_cast<uint64_t>(ticks);
+  }
   SolverBuffers b;
   memset(&b.a, 0, sizeof b.a);
   if ((st = prepare_solver(stream, n, s, d, k, n_samples, sp.cand_cap, true, true, true, true,
-                           final_grid, sample_slots(n, s, d, n_samples, sp.cand_cap), &b)) != BM_OK)
+                           final_grid, sbatch, &b)) != BM_OK)
     return st;
   SolverArgs& a = b.a;
   a.X = X;
@@ -502,6 +753,8 @@ bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int
   a.do_lloyd = 1;
   a.do_keep = 1;
   a.init_incumbent = o.resume ? 0 : 1;
+  a.init_forgy = o.init_method == BM_INIT_FORGY ? 1 : 0;
+  a.budget_ticks = budget_ticks;
   a.sums_in_lds = sp.sums_in_lds;
   a.c64_in_lds = sp.c64_in_lds;
   a.cand_cap = sp.cand_cap;
@@ -521,7 +774,8 @@ bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int
   BM_HIP(hipEventRecord(ev[0], stream));
   // every sample drawn up front by ordinary launches when they all have a slot
   const int pmode = g_presample_mode.load();
-  if (pmode != 1 && a.sbatch == a.T && a.T <= 65535) st = launch_presample(a, sp.lds, stream, pmode == 2);
+  if (pmode != 1 && !budget && a.sbatch == a.T && a.T <= 65535)
+    st = launch_presample(a, sp.lds, stream, pmode == 2);
   if (st == BM_OK) st = launch_solver(a, sp.grid, sp.lds, stream);
   if (st != BM_OK) {
     for (auto& e : ev) (void)hipEventDestroy(e);
@@ -556,14 +810,34 @@ bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int
     BM_HIP(hipMemcpyAsync(degenerate, a.deg_inc, size_t(k), hipMemcpyDeviceToHost, stream));
   if (o.sample_f)
     BM_HIP(hipMemcpyAsync(o.sample_f, a.sample_f, sizeof(double) * n_samples, hipMemcpyDeviceToHost, stream));
+  std::vector<uint8_t> deg_host(static_cast<size_t>(k));
+  if (polish)
+    BM_HIP(hipMemcpyAsync(deg_host.data(), a.deg_inc, size_t(k), hipMemcpyDeviceToHost, stream));
   int32_t code = 0;
   st = check_solver_error(a, stream, &code);
   memcpy(g_last_counters, counters, sizeof counters);
   const float ms_solver = elapsed_ms(ev[0], ev[1]);
-  const float ms_final = elapsed_ms(ev[1], ev[2]);
+  float ms_final = final_pass ? elapsed_ms(ev[1], ev[2]) : 0.f;
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (st != BM_OK) return st;
   if (fst != BM_OK) return fst;
+  int32_t polish_passes = 0;
+  if (polish) {
+    // Sec. 3.4: K-means on all of X from the Big-means centroids (in place in
+    // the caller's buffer), one batched problem; its last assignment gives
+    // the labels and the objective of the returned centroids
+    const auto t0 = std::chrono::steady_clock::now();
+    InnerScratch inner;
+    const int64_t rows[1] = {n};
+    const int32_t ks[1] = {k};
+    double fp = 0.0;
+    bm_status pst = batched_run(1, static_cast<const float*>(X), d, rows, ks, centroids,
+                                deg_host.data(), o, labels, &fp, &polish_passes);
+    if (pst != BM_OK) return pst;
+    if (degenerate) memcpy(degenerate, deg_host.data(), size_t(k));
+    sse_host = fp;
+    ms_final = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
   if (sse) *sse = sse_host;
   if (stats) {
     stats->samples = static_cast<int32_t>(counters[kCntSamples]);
@@ -577,6 +851,7 @@ bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int
     stats->ms_solver = ms_solver;
     stats->ms_final = ms_final;
     stats->rechecked = static_cast<int64_t>(nrecheck);
+    stats->final_passes = polish_passes;
     int dev = 0, khz = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0) {
@@ -833,217 +1108,12 @@ bm_status kmeans_lloyd_batched(int32_t n_solves, const float* P, int32_t d, cons
   bm_options o;
   bm_status st = resolve(opt_in, &o);
   if (st != BM_OK) return st;
-  if (n_solves < 1 || d < 1) return set_error(BM_EINVAL, "need n_solves >= 1 and d >= 1");
-  if (!P || !s || !k || !C || !deg) return set_error(BM_EINVAL, "P, s, k, C and deg are required");
-  if (padded_dim(d) < 0) return set_error(BM_ENOTSUP, "d = %d exceeds the limit of 256", d);
-  std::vector<int64_t> sv_s(n_solves);
-  std::vector<BatchSolve> hs(n_solves);
-  int64_t rows = 0, ktot = 0;
-  int kmax = 0;
-  for (int j = 0; j < n_solves; ++j) {
-    if (s[j] < 1 || k[j] < 1 || k[j] > s[j])
-      return set_error(BM_EINVAL, "solve %d: need 1 <= k <= s (s=%lld, k=%d)", j, (long long)s[j], k[j]);
-    int active = 0;
-    for (int q = 0; q < k[j]; ++q) active += deg[ktot + q] ? 0 : 1;
-    if (!active) return set_error(BM_EINVAL, "solve %d: every centroid is degenerate", j);
-    sv_s[j] = s[j];
-    memset(&hs[j], 0, sizeof(BatchSolve));
-    hs[j].row0 = rows;
-    hs[j].s = s[j];
-    hs[j].c0 = static_cast<int32_t>(ktot);
-    hs[j].k = k[j];
-    hs[j].status = kSolveRunning;
-    hs[j].iter = 1;
-    hs[j].f_prev = __builtin_inf();
-    rows += s[j];
-    ktot += k[j];
-    kmax = k[j] > kmax ? k[j] : kmax;
-    if (rows > 2147483647LL || ktot > 2147483647LL)
-      return set_error(BM_EINVAL, "more than 2^31 rows or centroids in the batch");
-  }
-  size_t lds_max = 0;
-  if ((st = max_lds_per_block(&lds_max)) != BM_OK) return st;
-  const bool sums_lds = batch_assign_lds(d, kmax, true) + 1024 <= lds_max;
-  if (!sums_lds && batch_assign_lds(d, kmax, false) + 1024 > lds_max)
-    return set_error(BM_ENOTSUP, "k x d = %d x %d centroids do not fit in one workgroup's LDS", kmax, d);
-  hipStream_t user = static_cast<hipStream_t>(o.stream);
   std::lock_guard<std::mutex> lock(g_mu);
-  int grid = 0;
-  if ((st = batch_assign_grid(d, kmax, sums_lds, &grid)) != BM_OK) return st;
-
-  // scratch: solve states, work list (sized for the smallest tile), tile
-  // objectives, FP64 sums, counts, FP64 means, flags, running counter
-  constexpr int kMinTile = 256;
-  int64_t max_tiles = 0;
-  for (int j = 0; j < n_solves; ++j) max_tiles += (s[j] + kMinTile - 1) / kMinTile;
-  BatchSolve* sv_d = nullptr;
-  int32_t* tiles_d = nullptr;
-  double* tile_f = nullptr;
-  double* sums = nullptr;
-  int32_t* cnt = nullptr;
-  double* c64 = nullptr;
-  float* cpad = nullptr;
-  float* ppad = nullptr;
-  uint8_t* deg_d = nullptr;
-  int* running = nullptr;
-  char* base = nullptr;
-  for (int round = 0; round < 2; ++round) {
-    Layout L;
-    L.base = base;
-    sv_d = L.take<BatchSolve>(n_solves);
-    tiles_d = L.take<int32_t>(max_tiles);
-    tile_f = L.take<double>(max_tiles);
-    sums = L.take<double>(ktot * padded_dim(d));
-    cnt = L.take<int32_t>(ktot);
-    c64 = L.take<double>(ktot * d);
-    cpad = L.take<float>(ktot * padded_dim(d));
-    ppad = L.take<float>(padded_dim(d) == d ? 1 : rows * padded_dim(d));
-    deg_d = L.take<uint8_t>(ktot);
-    running = L.take<int>(1);
-    if (round == 0) {
-      base = static_cast<char*>(scratch_get(L.off + 256, user, &st));
-      if (!base) return st;
-    }
-  }
-  // an internal stream (capturable; default priority) ordered after the caller's
-  hipStream_t stream = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  auto cleanup = [&]() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (ev_in) (void)hipEventDestroy(ev_in);
-    if (ev_out) (void)hipEventDestroy(ev_out);
-    if (stream) (void)hipStreamDestroy(stream);
-  };
-  auto fail = [&](bm_status code) {
-    if (stream) (void)hipStreamSynchronize(stream);
-    cleanup();
-    return code;
-  };
-#define BM_HIPB(call)                                                                          \
-  do {                                                                                         \
-    const hipError_t e_ = (call);                                                              \
-    if (e_ != hipSuccess)                                                                      \
-      return fail(set_error(BM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)));       \
-  } while (0)
-  BM_HIPB(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
-  BM_HIPB(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
-  BM_HIPB(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
-  BM_HIPB(hipEventRecord(ev_in, user));
-  BM_HIPB(hipStreamWaitEvent(stream, ev_in, 0));
-  BM_HIPB(hipMemcpyAsync(deg_d, deg, static_cast<size_t>(ktot), hipMemcpyHostToDevice, stream));
-  BM_HIPB(hipMemsetAsync(sums, 0, sizeof(double) * ktot * padded_dim(d), stream));
-  BM_HIPB(hipMemsetAsync(cnt, 0, sizeof(int32_t) * ktot, stream));
-  if ((st = launch_batch_init(C, c64, cpad, ktot, d, stream)) != BM_OK) return fail(st);
-  // rows DM wide for guard-free loads (a copy only when d is not already DM)
-  const float* Pp = P;
-  if (padded_dim(d) != d) {
-    if ((st = launch_pad_rows(P, ppad, rows, d, stream)) != BM_OK) return fail(st);
-    Pp = ppad;
-  }
-
-  // rows per tile: tuned once per shape by timing a dry assignment pass
-  std::vector<int32_t> tile_solve, tile0, ntiles;
-  const BatchShape shape{d, kmax, n_solves, rows};
-  int tile_rows = 0;
-  auto it_cache = g_tile_cache.find(shape);
-  auto upload = [&](int tr) -> bm_status {
-    const int nt = build_tiles(sv_s, tr, &tile_solve, &tile0, &ntiles);
-    for (int j = 0; j < n_solves; ++j) {
-      hs[j].tile0 = tile0[j];
-      hs[j].ntiles = ntiles[j];
-    }
-    BM_HIP(hipMemcpyAsync(tiles_d, tile_solve.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, stream));
-    BM_HIP(hipMemcpyAsync(sv_d, hs.data(), sizeof(BatchSolve) * n_solves, hipMemcpyHostToDevice, stream));
-    BM_HIP(hipStreamSynchronize(stream));  // the host vectors are reused
-    return BM_OK;
-  };
-  if (it_cache != g_tile_cache.end()) {
-    tile_rows = it_cache->second;
-  } else if (rows < 65536) {
-    tile_rows = 512;
-  } else {
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    BM_HIPB(hipEventCreate(&t0));
-    BM_HIPB(hipEventCreate(&t1));
-    float best = 0.f;
-    for (int tr : {256, 512, 1024, 2048, 4096}) {
-      bm_status su = upload(tr);
-      if (su != BM_OK) return fail(su);
-      const int nt = static_cast<int>(tile_solve.size());
-      float ms = 0.f;
-      for (int rep = 0; rep < 2 && su == BM_OK; ++rep) {  // first run warms caches
-        BM_HIPB(hipEventRecord(t0, stream));
-        su = launch_batch_assign(Pp, d, C, cpad, deg_d, sv_d, tiles_d, nt, tr, kmax, sums_lds, sums,
-                                 cnt, tile_f, nullptr, 1, grid, stream);
-        BM_HIPB(hipEventRecord(t1, stream));
-        BM_HIPB(hipEventSynchronize(t1));
-        BM_HIPB(hipEventElapsedTime(&ms, t0, t1));
-      }
-      if (su != BM_OK) return fail(su);
-      if (tile_rows == 0 || ms < best) {
-        best = ms;
-        tile_rows = tr;
-      }
-    }
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    g_tile_cache[shape] = tile_rows;
-  }
-  if ((st = upload(tile_rows)) != BM_OK) return fail(st);
-  const int nt = static_cast<int>(tile_solve.size());
-
-  // one round = assignment + update, captured once and launched per round
-  BM_HIPB(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-  bm_status cs = launch_batch_assign(Pp, d, C, cpad, deg_d, sv_d, tiles_d, nt, tile_rows, kmax,
-                                     sums_lds, sums, cnt, tile_f, labels, 0, grid, stream);
-  if (cs == BM_OK)
-    cs = launch_batch_update(sv_d, n_solves, tile_f, sums, cnt, C, cpad, c64, deg_d, d, o.max_iter,
-                             o.tol, o.stop_rule, running, stream);
-  const hipError_t ce = hipStreamEndCapture(stream, &graph);
-  if (cs != BM_OK) return fail(cs);
-  if (ce != hipSuccess)
-    return fail(set_error(BM_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce)));
-  BM_HIPB(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-  int still = 1;
-  int rounds = 0;
-  hipEvent_t r0 = nullptr, r1 = nullptr;
-  BM_HIPB(hipEventCreate(&r0));
-  BM_HIPB(hipEventCreate(&r1));
-  g_last_batch_ms.clear();
-  for (; rounds <= o.max_iter && still; ++rounds) {
-    BM_HIPB(hipMemsetAsync(running, 0, sizeof(int), stream));
-    BM_HIPB(hipEventRecord(r0, stream));
-    BM_HIPB(hipGraphLaunch(exec, stream));
-    BM_HIPB(hipEventRecord(r1, stream));
-    BM_HIPB(hipMemcpyAsync(&still, running, sizeof(int), hipMemcpyDeviceToHost, stream));
-    BM_HIPB(hipStreamSynchronize(stream));
-    g_last_batch_ms.push_back(elapsed_ms(r0, r1));
-  }
-  (void)hipEventDestroy(r0);
-  (void)hipEventDestroy(r1);
-  if (still) return fail(set_error(BM_EDEVICE, "batched Lloyd did not finish in max_iter + 1 rounds"));
-  BM_HIPB(hipMemcpyAsync(hs.data(), sv_d, sizeof(BatchSolve) * n_solves, hipMemcpyDeviceToHost, stream));
-  BM_HIPB(hipMemcpyAsync(deg, deg_d, static_cast<size_t>(ktot), hipMemcpyDeviceToHost, stream));
-  BM_HIPB(hipEventRecord(ev_out, stream));
-  BM_HIPB(hipStreamWaitEvent(user, ev_out, 0));
-  BM_HIPB(hipStreamSynchronize(stream));
-#undef BM_HIPB
-  for (int j = 0; j < n_solves; ++j) {
-    if (hs[j].status != kSolveDone) return fail(set_error(BM_EDEVICE, "solve %d did not finish", j));
-    if (f) f[j] = hs[j].f;
-    if (passes) passes[j] = hs[j].passes;
-  }
-  g_last_batch_rounds = rounds;
-  g_last_batch_tile = tile_rows;
-  cleanup();
-  return BM_OK;
+  return batched_run(n_solves, P, d, s, k, C, deg, o, labels, f, passes);
 }
 
 // Rounds and rows per tile of the last kmeans_lloyd_batched on this thread
-// (diagnostics; not declared in the public header).
+// (declared in include/bigmeans_debug.h, as the next one).
 int32_t bm_debug_batch_info(int32_t* rounds, int32_t* tile_rows) {
   if (rounds) *rounds = g_last_batch_rounds;
   if (tile_rows) *tile_rows = g_last_batch_tile;
@@ -1053,6 +1123,273 @@ int32_t bm_debug_batch_info(int32_t* rounds, int32_t* tile_rows) {
 // Device time (ms) of round i of the last kmeans_lloyd_batched (0 if out of range).
 double bm_debug_batch_round_ms(int32_t i) {
   return (i >= 0 && static_cast<size_t>(i) < g_last_batch_ms.size()) ? g_last_batch_ms[i] : 0.0;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Collective parallel Big-means (Sec. 3.6, third scheme) and the sample-size
+// rule of thumb (Sec. 5), composed from the kernels above.
+
+namespace bm {
+
+// Device buffer owned for the duration of one call.
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  bm_status alloc(size_t bytes) {
+    if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      return set_error(BM_ENOMEM, "cannot allocate %zu bytes of device memory", bytes);
+    }
+    return BM_OK;
+  }
+};
+
+// The body of bigmeans_fit_collective after validation; the caller holds g_mu.
+static bm_status collective_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int32_t W,
+                                int32_t R, uint64_t seed, const bm_options& o, float* centroids,
+                                double* sse, int32_t* labels, uint8_t* degenerate, bm_stats* stats,
+                                double* worker_f) {
+  bm_status st = BM_OK;
+  hipStream_t stream = static_cast<hipStream_t>(o.stream);
+  SolverPlan sp;
+  if ((st = plan_solver(d, k, s, n, o.grid, &sp)) != BM_OK) return st;
+  if (sample_slots(n, s, d, W, sp.cand_cap) < W)
+    return set_error(BM_ENOTSUP, "the %d samples of a round do not fit the sample buffers", W);
+  const bool final_pass = sse || labels;
+  const bool final_mfma = final_pass && o.precision == BM_PREC_BF16_MFMA;
+  int final_grid = final_pass ? assign_grid(n) : 0;
+  if (final_mfma && (st = plan_assign_mfma(X, n, d, k, &final_grid)) != BM_OK) return st;
+  SolverBuffers b;
+  memset(&b.a, 0, sizeof b.a);
+  if ((st = prepare_solver(stream, n, s, d, k, W, sp.cand_cap, true, true, true, true, final_grid, W,
+                           &b)) != BM_OK)
+    return st;
+  // the workers' centroids and flags, and the incumbent's flags on the device
+  const size_t cbytes = sizeof(float) * static_cast<size_t>(k) * d;
+  DevBuf cw, degw_d;
+  if ((st = cw.alloc(cbytes * W)) != BM_OK) return st;
+  if ((st = degw_d.alloc(static_cast<size_t>(k) * W)) != BM_OK) return st;
+  float* Cw = static_cast<float*>(cw.p);
+  uint8_t* Dw = static_cast<uint8_t*>(degw_d.p);
+  std::vector<uint8_t> deg_inc(static_cast<size_t>(k), 1), degw(static_cast<size_t>(k) * W);
+  std::vector<int64_t> s_arr(W, s);
+  std::vector<int32_t> k_arr(W, k), passes(W);
+  std::vector<double> fw(W);
+  double f_opt = __builtin_inf();
+  int64_t replaced = 0, lloyd_iters = 0, reseeded = 0, seed_nd = 0;
+  float* const Pb = b.a.P;
+  // the incumbent lives in the caller's buffer: all degenerate (NaN) at first
+  BM_HIP(hipMemsetAsync(centroids, 0xFF, cbytes, stream));
+  const int pmode = g_presample_mode.load();
+
+  for (int32_t r = 0; r < R; ++r) {
+    const uint32_t t0 = static_cast<uint32_t>(static_cast<int64_t>(r) * W);
+    // (1) the round's W samples, t = r W .. r W + W - 1, rows into slots w
+    SolverArgs a = b.a;
+    a.X = X;
+    a.n = n;
+    a.s = s;
+    a.d = d;
+    a.k = k;
+    a.x_bf16 = o.x_dtype == BM_BF16;
+    a.T = W;
+    a.seed = seed;
+    a.t0 = static_cast<int32_t>(t0);
+    a.max_iter = o.max_iter;
+    a.tol = o.tol;
+    a.stop_rule = o.stop_rule;
+    a.trials = o.n_local_trials;
+    a.cmp_rule = BM_CMP_FOPT;
+    a.do_sample = 1;
+    a.do_gather = 1;
+    a.init_incumbent = 1;
+    a.init_forgy = o.init_method == BM_INIT_FORGY ? 1 : 0;
+    a.sums_in_lds = sp.sums_in_lds;
+    a.c64_in_lds = sp.c64_in_lds;
+    a.cand_cap = sp.cand_cap;
+    a.win_lo = sp.win_lo;
+    a.win_hi = sp.win_hi;
+    a.spin_limit = o.spin_limit ? o.spin_limit : kDefaultSpinLimit;
+    a.presampled = 0;
+    BM_HIP(hipMemsetAsync(b.a.bar, 0, b.ctrl_bytes, stream));
+    if (pmode != 1 && W <= 65535) st = launch_presample(a, sp.lds, stream, pmode == 2);
+    if (st == BM_OK) st = launch_solver(a, sp.grid, sp.lds, stream);
+    if (st != BM_OK) return st;
+    if ((st = check_solver_error(a, stream, nullptr)) != BM_OK) return st;
+    // (2) every worker starts from the incumbent; its degenerate slots are
+    // reinitialised on its own sample with its own draws (t = r W + w)
+    for (int32_t w = 0; w < W; ++w) {
+      BM_HIP(hipMemcpyAsync(Cw + static_cast<size_t>(w) * k * d, centroids, cbytes,
+                            hipMemcpyDeviceToDevice, stream));
+      memcpy(degw.data() + static_cast<size_t>(w) * k, deg_inc.data(), size_t(k));
+    }
+    BM_HIP(hipMemcpyAsync(Dw, degw.data(), degw.size(), hipMemcpyHostToDevice, stream));
+    bool any_deg = false;
+    for (int j = 0; j < k; ++j) any_deg = any_deg || deg_inc[j];
+    if (any_deg) {
+      for (int32_t w = 0; w < W; ++w) {
+        SolverArgs q = a;
+        q.P = Pb + static_cast<size_t>(w) * s * d;
+        q.T = 1;
+        q.t0 = static_cast<int32_t>(t0 + w);
+        q.sbatch = 1;
+        q.do_sample = 0;
+        q.do_gather = 0;
+        q.do_seed = 1;
+        q.init_incumbent = 0;
+        q.presampled = 0;
+        q.Cinc = Cw + static_cast<size_t>(w) * k * d;
+        q.deg_inc = Dw + static_cast<size_t>(w) * k;
+        BM_HIP(hipMemsetAsync(b.a.bar, 0, b.ctrl_bytes, stream));
+        if ((st = launch_solver(q, sp.grid, sp.lds, stream)) != BM_OK) return st;
+        int64_t cnt[kNumCounters];
+        BM_HIP(hipMemcpyAsync(cnt, q.counters, sizeof cnt, hipMemcpyDeviceToHost, stream));
+        if ((st = check_solver_error(q, stream, nullptr)) != BM_OK) return st;
+        reseeded += cnt[kCntReseeded];
+        seed_nd += cnt[kCntND];
+      }
+      BM_HIP(hipMemcpyAsync(degw.data(), Dw, degw.size(), hipMemcpyDeviceToHost, stream));
+      BM_HIP(hipStreamSynchronize(stream));
+    }
+    // (3) K-means of all workers at once (the batched kernels)
+    {
+      InnerScratch inner;
+      if ((st = batched_run(W, Pb, d, s_arr.data(), k_arr.data(), Cw, degw.data(), o, nullptr,
+                            fw.data(), passes.data())) != BM_OK)
+        return st;
+    }
+    // (4) the round's best worker (ties to the lowest) against f_opt (Alg. 1)
+    int32_t best = 0;
+    for (int32_t w = 1; w < W; ++w)
+      if (fw[w] < fw[best]) best = w;
+    for (int32_t w = 0; w < W; ++w) {
+      lloyd_iters += passes[w];
+      if (worker_f) worker_f[static_cast<size_t>(r) * W + w] = fw[w];
+    }
+    if (f_opt > fw[best]) {
+      BM_HIP(hipMemcpyAsync(centroids, Cw + static_cast<size_t>(best) * k * d, cbytes,
+                            hipMemcpyDeviceToDevice, stream));
+      memcpy(deg_inc.data(), degw.data() + static_cast<size_t>(best) * k, size_t(k));
+      f_opt = fw[best];
+      ++replaced;
+    }
+  }
+  // final assignment (Alg. 1 last step)
+  double sse_host = 0.0;
+  if (final_pass) {
+    BM_HIP(hipMemcpyAsync(b.a.deg_inc, deg_inc.data(), size_t(k), hipMemcpyHostToDevice, stream));
+    if (final_mfma) {
+      st = launch_assign_mfma(static_cast<const uint16_t*>(X), n, d, centroids, b.a.deg_inc, k,
+                              labels, nullptr, b.partial, b.done, b.sse_dev, b.rechecked, final_grid,
+                              stream);
+    } else {
+      st = launch_assign(X, o.x_dtype == BM_BF16, n, d, centroids, b.a.deg_inc, k, labels, nullptr,
+                         b.partial, b.done, b.sse_dev, final_grid, stream);
+    }
+    if (st != BM_OK) return st;
+    BM_HIP(hipMemcpyAsync(&sse_host, b.sse_dev, sizeof(double), hipMemcpyDeviceToHost, stream));
+  }
+  BM_HIP(hipStreamSynchronize(stream));
+  if (sse) *sse = sse_host;
+  if (degenerate) memcpy(degenerate, deg_inc.data(), size_t(k));
+  if (stats) {
+    memset(reinterpret_cast<char*>(stats) + sizeof(uint32_t), 0, sizeof(bm_stats) - sizeof(uint32_t));
+    stats->samples = static_cast<int32_t>(static_cast<int64_t>(R) * W);
+    stats->replacements = static_cast<int32_t>(replaced);
+    stats->grid = sp.grid;
+    stats->lloyd_iters = lloyd_iters;
+    stats->reseeded = reseeded;
+    stats->n_d = -1;  // the batched kernels do not count distance evaluations
+    stats->f_opt = f_opt;
+  }
+  return BM_OK;
+}
+
+}  // namespace bm
+
+extern "C" {
+
+bm_status bigmeans_fit_collective(const void* X, int64_t n, int32_t d, int32_t k, int64_t s,
+                                  int32_t n_workers, int32_t n_rounds, uint64_t seed,
+                                  const bm_options* opt_in, float* centroids, double* sse,
+                                  int32_t* labels, uint8_t* degenerate, bm_stats* stats,
+                                  double* worker_f) {
+  clear_error();
+  if (n_workers < 1 || n_workers > 1024 || n_rounds < 1)
+    return set_error(BM_EINVAL, "need 1 <= n_workers <= 1024 and n_rounds >= 1");
+  const int64_t total = static_cast<int64_t>(n_workers) * n_rounds;
+  if (total > 2147483647LL) return set_error(BM_EINVAL, "n_rounds x n_workers exceeds 2^31");
+  bm_options o;
+  bm_status st = fit_validate(X, n, d, k, s, static_cast<int32_t>(total), opt_in, centroids, nullptr,
+                              stats, &o);
+  if (st != BM_OK) return st;
+  if (o.compare_rule != BM_CMP_FOPT)
+    return set_error(BM_ENOTSUP, "the collective mode compares with f_opt (BM_CMP_FOPT) only");
+  std::lock_guard<std::mutex> lock(g_mu);
+  return collective_run(X, n, d, k, s, n_workers, n_rounds, seed, o, centroids, sse, labels,
+                        degenerate, stats, worker_f);
+}
+
+bm_status bigmeans_sample_size_sweep(const void* X, int64_t n, int32_t d, int32_t k,
+                                     int64_t s_min, int64_t s_max, int32_t n_samples,
+                                     uint64_t seed, const bm_options* opt_in, float* centroids,
+                                     double* sse, int32_t* labels, uint8_t* degenerate,
+                                     int64_t* s_best, int64_t* s_tried, double* sse_tried,
+                                     int32_t max_tried, int32_t* n_tried) {
+  clear_error();
+  if (!sse || !s_best) return set_error(BM_EINVAL, "sse and s_best are required");
+  if (s_min > s_max) return set_error(BM_EINVAL, "need s_min <= s_max");
+  bm_options o;
+  bm_status st = fit_validate(X, n, d, k, s_min, n_samples, opt_in, centroids, nullptr, nullptr, &o);
+  if (st != BM_OK) return st;
+  if (o.final_mode != BM_FINAL_ASSIGN)
+    return set_error(BM_EINVAL, "the sweep compares final assignments (final_mode BM_FINAL_ASSIGN)");
+  o.resume = 0;
+  o.t_start = 0;
+  o.sample_idx = nullptr;
+  o.sample_f = nullptr;
+  if (s_max > n) s_max = n;
+  hipStream_t stream = static_cast<hipStream_t>(o.stream);
+  DevBuf ct, lt;
+  const size_t cbytes = sizeof(float) * static_cast<size_t>(k) * d;
+  if ((st = ct.alloc(cbytes)) != BM_OK) return st;
+  if (labels && (st = lt.alloc(sizeof(int32_t) * static_cast<size_t>(n))) != BM_OK) return st;
+  std::vector<uint8_t> degt(static_cast<size_t>(k));
+  std::lock_guard<std::mutex> lock(g_mu);
+  double best = __builtin_inf();
+  int64_t bs = -1;
+  int32_t m = 0;
+  for (int64_t s = s_min;;) {
+    double f = 0.0;
+    st = fit_run(X, n, d, k, s, n_samples, seed, o, static_cast<float*>(ct.p), &f,
+                 labels ? static_cast<int32_t*>(lt.p) : nullptr, degt.data(), nullptr, 0);
+    if (st != BM_OK) return st;
+    if (m < max_tried) {
+      if (s_tried) s_tried[m] = s;
+      if (sse_tried) sse_tried[m] = f;
+    }
+    ++m;
+    if (!(f < best)) break;  // no improvement: the sweet spot is behind
+    best = f;
+    bs = s;
+    BM_HIP(hipMemcpyAsync(centroids, ct.p, cbytes, hipMemcpyDeviceToDevice, stream));
+    if (labels)
+      BM_HIP(hipMemcpyAsync(labels, lt.p, sizeof(int32_t) * static_cast<size_t>(n),
+                            hipMemcpyDeviceToDevice, stream));
+    if (degenerate) memcpy(degenerate, degt.data(), size_t(k));
+    if (s >= s_max) break;
+    s = (s > s_max / 2) ? s_max : 2 * s;
+  }
+  BM_HIP(hipStreamSynchronize(stream));
+  *sse = best;
+  *s_best = bs;
+  if (n_tried) *n_tried = m < max_tried ? m : max_tried;
+  return BM_OK;
 }
 
 }  // extern "C"

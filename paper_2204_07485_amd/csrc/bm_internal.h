@@ -68,6 +68,10 @@ struct SolverArgs {
   int32_t do_lloyd;
   int32_t do_keep;
   int32_t init_incumbent;
+  int32_t init_forgy;        // 1: degenerate slots take uniform rows (Forgy), not K-means++
+  uint64_t budget_ticks;     // > 0: stop before a sample once this many wall-clock
+                             // ticks have passed since the launch (sample 0 always runs)
+  int32_t* stop_flag;        // workgroup 0's budget decision, read after a grid barrier
   int32_t sums_in_lds;
   int32_t c64_in_lds;
   int64_t cand_cap;          // capacity of the global candidate list

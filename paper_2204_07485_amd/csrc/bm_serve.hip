@@ -838,9 +838,13 @@ bm_status bm_ctx_submit(bm_ctx* c, const bm_job* job_in, int64_t* job_id) {
   bm_status st = fit_validate(J.X, J.n, J.d, J.k, J.s, J.n_samples, &J.opt, J.centroids,
                               J.degenerate, J.stats, &j->opt);
   if (st != BM_OK) return st;
+  if (j->opt.final_mode != BM_FINAL_ASSIGN)
+    return set_error(BM_ENOTSUP, "served jobs end with the final assignment (BM_FINAL_ASSIGN)");
   if (c->mode == BM_SERVE_ROUNDS) {
     if (j->opt.compare_rule != BM_CMP_FOPT)
       return set_error(BM_ENOTSUP, "round-batched serving compares with f_opt only (BM_CMP_FOPT)");
+    if (j->opt.init_method != BM_INIT_KMEANSPP || j->opt.time_budget_ms > 0.0)
+      return set_error(BM_ENOTSUP, "round-batched serving reseeds with K-means++ and has no time budget");
     if (J.s > c->round_max_s || J.k > c->round_max_k)
       return set_error(BM_ENOTSUP, "s = %lld or k = %d above the context's round_max_s / round_max_k",
                        static_cast<long long>(J.s), J.k);

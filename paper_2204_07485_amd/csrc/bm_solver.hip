@@ -1265,6 +1265,32 @@ __device__ __forceinline__ bool lloyd_phase(const SolverArgs& a, const LdsPlan& 
   return true;
 }
 
+// Another initialisation of the degenerate slots (Sec. 3.3 allows other
+// strategies than K-means++): each degenerate slot, ascending, takes the
+// sample row at a uniformly drawn index (draw q of sample t of the K-means++
+// stream; independent draws, so two slots may take the same row and the later
+// one then empties).  Every workgroup draws the same indices; no distances and
+// no grid barrier are needed.
+template <int DM>
+__device__ __forceinline__ void forgy_phase(const SolverArgs& a, Lds& L, uint32_t t, int64_t& nres) {
+  const int d = a.d;
+  const int k = a.k;
+  uint64_t q = 0;
+  for (int j = 0; j < k; ++j) {
+    if (!L.degf[j]) continue;
+    const int64_t pick =
+        static_cast<int64_t>(below_from_word(seed_draw(a.seed, t, q), static_cast<uint64_t>(a.s)));
+    ++q;
+    for (int tdim = threadIdx.x; tdim < DM; tdim += kBlock)
+      L.C[j * DM + tdim] = (tdim < d) ? a.P[static_cast<size_t>(pick) * d + tdim] : 0.f;
+    __syncthreads();
+    if (threadIdx.x == 0) L.degf[j] = 0;
+    __syncthreads();
+    nres += 1;
+  }
+  rebuild_active(L, k);
+}
+
 // ---------------------------------------------------------------------------
 
 // The incumbent into LDS; a degenerate slot is filled with NaN so that no
@@ -1326,6 +1352,7 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
   float* const Pb = a.P;
   int32_t* const idxb = a.idx;
   bool stored = false;  // the previous sample replaced the incumbent (grid-uniform)
+  const uint64_t clk_launch = wall_clock64();
   // every sample was drawn before this launch (presample_* kernels) unless a
   // predicted window missed; then the samples are drawn here as usual
   const bool presampled =
@@ -1333,6 +1360,19 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
   for (int tt = 0; ok && tt < a.T; ++tt) {
     const uint32_t t = static_cast<uint32_t>(a.t0 + tt);
     const int slot = tt % a.sbatch;
+    if (a.budget_ticks && tt > 0) {
+      // time budget (the CPU-time stop condition of Sec. 5): workgroup 0
+      // reads its clock, and every workgroup takes its decision after a
+      // barrier, so all stop before the same sample
+      if (g == 0 && tid == 0)
+        __hip_atomic_store(a.stop_flag, (wall_clock64() - clk_launch) >= a.budget_ticks ? 1 : 0,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ok = sync_grid(a);
+      if (!ok) break;
+      if (__hip_atomic_load(a.stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      // the flag is written again before the next sample; no workgroup reads
+      // it until that sample's barrier
+    }
     uint64_t clk0 = wall_clock64();
     if (a.do_sample && slot == 0 && !presampled) {
       const int nb = a.T - tt < a.sbatch ? a.T - tt : a.sbatch;
@@ -1376,8 +1416,12 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
     }
     clk0 = wall_clock64();
     if (a.do_seed && L.misc[0] < a.k) {
-      ok = reseed_phase<DM>(a, L, t, r0, r1, cached, rc, c_nd, c_reseeded);
-      if (!ok) break;
+      if (a.init_forgy) {
+        forgy_phase<DM>(a, L, t, c_reseeded);
+      } else {
+        ok = reseed_phase<DM>(a, L, t, r0, r1, cached, rc, c_nd, c_reseeded);
+        if (!ok) break;
+      }
     }
     clk1 = wall_clock64();
     c_tseed += clk1 - clk0;
@@ -1545,7 +1589,7 @@ bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t s
                        !a.wg_off || !a.thr || !a.hist || !a.cand_count || !a.smiss)) ||
       (rows && (!a.w || !a.dcache)) || !a.Cinc || !a.deg_inc || !a.f_opt || !a.c64 || !a.sums ||
       !a.cnt || !a.sse_part || !a.wsum || !a.phi_part || !a.cand || !a.counters || !a.bar ||
-      !a.err || !a.sample_f || grid < 1 || grid > kMaxGrid)
+      !a.err || !a.sample_f || (a.budget_ticks && !a.stop_flag) || grid < 1 || grid > kMaxGrid)
     return set_error(BM_EINVAL, "solver launch with a missing buffer or bad grid %d", grid);
   const int dm = padded_dim(a.d);
   const void* fn = solver_fn(dm);

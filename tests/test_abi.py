@@ -56,7 +56,7 @@ def test_every_exported_symbol_is_declared(bm):
 
 def test_abi_version_and_struct_sizes(bm):
     lib = bm.load()
-    assert lib.bm_abi_version() == 1
+    assert lib.bm_abi_version() == 2
     o = bm.Options()
     assert lib.bm_default_options(ct.byref(o)) == 0
     assert o.struct_size == ct.sizeof(bm.Options)
