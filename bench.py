@@ -185,6 +185,42 @@ def mixed_precision(reps=5):
     }
 
 
+def collective_and_sweep(Xd, W, reps=3):
+    """The collective parallel form (Sec. 3.6, third scheme) on the medium
+    workload, 8 workers x 7 rounds, checked against the oracle's stored
+    result; and the sample-size rule of thumb (Sec. 5) from s = 5,000 with 50
+    samples per size."""
+    from paper_2204_07485_amd import bigmeans
+    import torch
+    with open(os.path.join(ROOT, "tests", "golden", "medium_collective.json")) as fh:
+        gold = json.load(fh)
+    kw = dict(max_iter=300, tol=1e-4, stop_rule=bigmeans.BM_STOP_REL_OBJ, n_local_trials=3)
+    bigmeans.bigmeans_fit_collective(Xd, W.k, W.s, gold["workers"], gold["rounds"], W.seed, **kw)
+    times, res = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = bigmeans.bigmeans_fit_collective(Xd, W.k, W.s, gold["workers"], gold["rounds"],
+                                               W.seed, **kw)
+        times.append((time.perf_counter() - t0) * 1e3)
+    rel = abs(res["sse"] - gold["sse"]) / gold["sse"]
+    ms = statistics.median(times)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sw = bigmeans.sample_size_sweep(Xd, W.k, 5_000, W.n, W.n_samples, W.seed, **kw)
+    sweep_ms = (time.perf_counter() - t0) * 1e3
+    return {
+        "collective": {"workload": f"medium, {gold['workers']} workers x {gold['rounds']} rounds",
+                       "ms": ms, "sse": res["sse"], "oracle_sse": gold["sse"],
+                       "sse_rel_err": rel, "time_to_oracle_sse_ms": ms if rel <= 1e-6 else None,
+                       "lloyd_iters": res["stats"]["lloyd_iters"],
+                       "samples": res["stats"]["samples"]},
+        "sample_size_sweep": {"workload": "medium, s = 5,000 doubling, 50 samples per size",
+                              "ms": sweep_ms, "s_best": sw["s_best"], "sse": sw["sse"],
+                              "tried": sw["tried"]},
+    }
+
+
 def final_passes(Xmed, gold, reps=5):
     """The full-data assignment pass (Alg. 1 last step) timed alone with HIP
     events, with the last-level cache flushed before each launch: the medium
@@ -451,6 +487,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    print("collective mode and sample-size sweep ...", file=sys.stderr, flush=True)
+    line.update(collective_and_sweep(Xd, W))
     if not args.no_final:
         print("final passes (cache flushed) ...", file=sys.stderr, flush=True)
         line["final_pass"] = final_passes(Xd, gold)

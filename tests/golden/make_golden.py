@@ -10,7 +10,11 @@ medium_fit.json (about half a minute): Big-means on the medium workload
 paper's stop rule (relative objective decrease <= 1e-4 or 300 rounds, Sec. 5)
 and three K-means++ candidates (Sec. 5), followed by the final assignment.
 
-bf16_fit.json (tens of minutes on all host cores; the threaded oracle build,
+medium_collective.json: the collective parallel form (Sec. 3.6, third scheme)
+on the medium workload: 8 workers x 7 rounds (56 samples), same stop rule and
+seeding, followed by the final assignment (threaded oracle build).
+
+bf16_fit.json (minutes on all host cores; the threaded oracle build,
 whose results are bit-identical to the single-threaded one): the same on the
 BF16 workload (5,000,000 x 128 stored as BF16, 100 components plus 10 %
 uniform outliers, k=100, s=200,000, 30 samples, seed 4); the oracle reads the
@@ -78,7 +82,32 @@ def bf16():
           flush=True)
 
 
+def collective():
+    W = synth.MEDIUM
+    X = synth.make_medium()
+    workers, rounds = 8, 7
+    t0 = time.time()
+    with oracle.threaded():
+        r = oracle.bigmeans_collective(X, W.k, W.s, workers, rounds, W.seed, max_iter=300,
+                                       tol=1e-4, stop_rule=oracle.ORC_STOP_REL_OBJ,
+                                       n_local_trials=3, want_labels=True)
+    secs = time.time() - t0
+    out = {
+        "workload": "medium, collective: 1,000,000 x 16, k=25, s=40,000, 8 workers x 7 rounds, "
+                    "seed 2, stop: relative objective decrease <= 1e-4 or 300 rounds",
+        "workers": workers, "rounds": rounds,
+        "sse": r["sse"], "f_opt": r["f_opt"], "worker_f": r["worker_f"].tolist(),
+        "deg": r["deg"].tolist(),
+        "C": np.where(np.isnan(r["C"]), None, r["C"]).tolist(),
+        "label_counts": np.bincount(r["labels"], minlength=W.k).tolist(),
+        "stats": r["stats"], "oracle_seconds": secs,
+    }
+    with open(os.path.join(HERE, "medium_collective.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(f"collective: sse={r['sse']!r} f_opt={r['f_opt']!r} in {secs:.1f}s", flush=True)
+
+
 if __name__ == "__main__":
     targets = sys.argv[1:] or ["medium"]
     for name in targets:
-        {"medium": medium, "bf16": bf16}[name]()
+        {"medium": medium, "bf16": bf16, "collective": collective}[name]()

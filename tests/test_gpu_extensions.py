@@ -125,7 +125,7 @@ def test_initialiser_mode_skips_the_final_pass():
     Xd = torch.from_numpy(X).cuda()
     full = bigmeans.bigmeans_fit(Xd, 20, 10_000, 8, 3)
     init = bigmeans.bigmeans_fit(Xd, 20, 10_000, 8, 3, want_labels=False, want_sse=False)
-    assert init["stats"]["ms_final"] == 0.0 and init["labels"] is None
+    assert init["stats"]["ms_final"] == 0.0 and init["labels"] is None  # no final pass ran
     assert torch.equal(full["centroids"].isnan(), init["centroids"].isnan())
     assert torch.equal(torch.nan_to_num(full["centroids"]), torch.nan_to_num(init["centroids"]))
     assert init["f_opt"] == full["f_opt"]
@@ -236,3 +236,28 @@ def test_sample_size_sweep_matches_oracle():
         assert_sse(a, b)
     assert got["s_best"] == best
     assert_sse(got["sse"], dict(tried)[best])
+
+
+def test_collective_medium_workload_matches_stored_oracle():
+    # the benchmark's collective configuration: the medium workload with 8
+    # workers x 7 rounds, against tests/golden/medium_collective.json
+    import json
+    import os
+    from paper_2204_07485_amd import bigmeans
+    with open(os.path.join(os.path.dirname(__file__), "golden", "medium_collective.json")) as fh:
+        gold = json.load(fh)
+    W = synth.MEDIUM
+    X = synth.make_medium()
+    got = bigmeans.bigmeans_fit_collective(torch.from_numpy(X).cuda(), W.k, W.s, gold["workers"],
+                                           gold["rounds"], W.seed, max_iter=300, tol=1e-4,
+                                           stop_rule=bigmeans.BM_STOP_REL_OBJ)
+    print(f"collective medium: gpu sse {got['sse']!r} oracle {gold['sse']!r}", flush=True)
+    bad = _first_bad(got["worker_f"].ravel(), np.array(gold["worker_f"]).ravel())
+    assert bad is None, f"worker objective diverges first at (round, worker) {divmod(bad, 8)}"
+    assert_sse(got["sse"], gold["sse"])
+    assert_sse(got["f_opt"], gold["f_opt"])
+    assert got["degenerate"].tolist() == gold["deg"]
+    for key in ("replacements", "reseeded", "lloyd_iters"):
+        assert got["stats"][key] == gold["stats"][key], key
+    Cg = np.array([[np.nan if v is None else v for v in row] for row in gold["C"]])
+    assert_centroids(got["centroids"].cpu().numpy(), Cg, np.array(gold["deg"]))
