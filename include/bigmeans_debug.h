@@ -22,6 +22,12 @@ extern "C" {
  * for a mode outside 0..2.  Process-wide. */
 int32_t bm_debug_presample(int32_t mode);
 
+/* BF16 points with BM_PREC_BF16_MFMA: 1 (default) runs the sample-level
+ * K-means on the matrix cores, 0 runs it on the FP32 persistent solver (both
+ * give the same labels).  Returns the previous setting, or -1 for another
+ * value.  Process-wide. */
+int32_t bm_debug_mfma_lloyd(int32_t on);
+
 /* Copies the first n raw device counters of this thread's last bigmeans_fit
  * (passes, reseeds, replacements, n_d, boundary draws, samples, sampler
  * passes, then per-phase clock ticks) into out.  BM_EINVAL for out NULL or

@@ -574,3 +574,12 @@ def debug_counters():
              15: "ticks_collect_wait", 16: "ticks_select", 17: "ticks_emit", 18: "ticks_assign",
              19: "ticks_flush"}
     return {v: int(out[k]) for k, v in names.items()}
+
+
+def debug_mfma_lloyd(on):
+    """BF16 matrix-core fits: 1 = sample-level K-means on the matrix cores
+    (default), 0 = on the FP32 persistent solver; returns the previous value."""
+    L = load()
+    L.bm_debug_mfma_lloyd.argtypes = [ct.c_int32]
+    L.bm_debug_mfma_lloyd.restype = ct.c_int32
+    return L.bm_debug_mfma_lloyd(on)

@@ -22,6 +22,9 @@ static thread_local int64_t g_last_counters[kNumCounters];
 // Presampling before the solver: 0 automatic, 1 never, 2 always report a
 // window miss (the solver then samples itself); a test hook, not in the header.
 static std::atomic<int> g_presample_mode{0};
+// BF16 matrix-core fits: 1 = the sample-level K-means on the matrix cores
+// (default), 0 = the FP32 persistent solver for it (a test hook).
+static std::atomic<int> g_mfma_lloyd{1};
 static thread_local int64_t g_last_rechecked = 0;
 static thread_local double g_last_assign_ms = 0.0;
 static thread_local int32_t g_last_batch_rounds = 0;
@@ -627,6 +630,11 @@ int32_t bm_debug_presample(int32_t mode) {
 }
 
 // Raw per-phase counters of the last bigmeans_fit on this thread.
+int32_t bm_debug_mfma_lloyd(int32_t on) {
+  if (on < 0 || on > 1) return -1;
+  return g_mfma_lloyd.exchange(on);
+}
+
 int32_t bm_debug_counters(int64_t* out, int32_t n) {
   if (!out || n < 1) return BM_EINVAL;
   for (int i = 0; i < n && i < kNumCounters; ++i) out[i] = g_last_counters[i];
@@ -691,6 +699,279 @@ size_t fit_scratch_bytes(int64_t n, int32_t d, int32_t k, int64_t s, int32_t n_s
   return b.bytes;
 }
 
+// Device buffers of the matrix-core sample K-means (one problem at a time).
+struct MfmaLloydBuffers {
+  uint16_t* p16 = nullptr;   // s x d BF16 rows of the sample
+  float* ppad = nullptr;     // s x DM FP32 rows when d != DM
+  int32_t* lab = nullptr;    // s labels from the matrix cores
+  BatchSolve* sv = nullptr;
+  int32_t* tiles = nullptr;
+  double* tile_f = nullptr;
+  double* sums = nullptr;    // k x DM
+  int32_t* cnt = nullptr;
+  double* c64 = nullptr;     // k x d
+  float* cpad = nullptr;     // k x DM
+  float* cw = nullptr;       // k x d: the sample's centroids
+  uint8_t* degw = nullptr;   // k
+  int* running = nullptr;
+};
+
+// bigmeans_fit for BF16 points with BM_PREC_BF16_MFMA (Alg. 1 with the
+// sample-level K-means on the matrix cores): all samples are drawn up front;
+// per sample the incumbent's degenerate slots are reseeded by the solver in
+// seed-only mode, then each K-means round is the matrix-core assignment
+// (labels equal to the FP32 path's), the batched kernel's FP64 accumulation
+// and objective for those labels, and its update with the stop rules; the
+// keep-the-best comparison runs on the host between samples.  *handled is
+// false (and nothing is done) when the shape does not suit this form.
+static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s,
+                              int32_t n_samples, uint64_t seed, const bm_options& o,
+                              float* centroids, double* sse, int32_t* labels, uint8_t* degenerate,
+                              bm_stats* stats, int grid_cap, bool* handled) {
+  *handled = false;
+  bm_status st = BM_OK;
+  hipStream_t stream = static_cast<hipStream_t>(o.stream);
+  SolverPlan sp;
+  if ((st = plan_solver(d, k, s, n, o.grid, &sp)) != BM_OK) return st;
+  if (grid_cap > 0 && sp.grid > grid_cap && (st = plan_solver(d, k, s, n, grid_cap, &sp)) != BM_OK)
+    return st;
+  const int T = n_samples;
+  if (T > 65535 || sample_slots(n, s, d, T, sp.cand_cap) < T) return BM_OK;
+  const int dm = padded_dim(d);
+  size_t lds_max = 0;
+  if ((st = max_lds_per_block(&lds_max)) != BM_OK) return st;
+  const bool sums_lds = batch_assign_lds(d, k, true) + 1024 <= lds_max;
+  if (!sums_lds && batch_assign_lds(d, k, false) + 1024 > lds_max) return BM_OK;
+  const bool final_pass = sse || labels;
+  int fgrid = 0;
+  if (final_pass && plan_assign_mfma(X, n, d, k, &fgrid) != BM_OK) {
+    clear_error();
+    return BM_OK;
+  }
+  constexpr int kTile = 1024;
+  const int ntiles = static_cast<int>((s + kTile - 1) / kTile);
+  // the sample buffers of this form, on the inner pool
+  MfmaLloydBuffers m;
+  {
+    InnerScratch inner;
+    char* base = nullptr;
+    for (int round = 0; round < 2; ++round) {
+      Layout L;
+      L.base = base;
+      m.p16 = L.take<uint16_t>(static_cast<size_t>(s) * d + 8);
+      m.ppad = L.take<float>(dm == d ? 1 : static_cast<size_t>(s) * dm);
+      m.lab = L.take<int32_t>(s);
+      m.sv = L.take<BatchSolve>(1);
+      m.tiles = L.take<int32_t>(ntiles);
+      m.tile_f = L.take<double>(ntiles);
+      m.sums = L.take<double>(static_cast<size_t>(k) * dm);
+      m.cnt = L.take<int32_t>(k);
+      m.c64 = L.take<double>(static_cast<size_t>(k) * d);
+      m.cpad = L.take<float>(static_cast<size_t>(k) * dm);
+      m.cw = L.take<float>(static_cast<size_t>(k) * d);
+      m.degw = L.take<uint8_t>(k);
+      m.running = L.take<int>(1);
+      if (round == 0) {
+        base = static_cast<char*>(scratch_get(L.off + 256, stream, &st));
+        if (!base) return st;
+      }
+    }
+  }
+  int mgrid = 0, bgrid = 0;
+  if (plan_assign_mfma(m.p16, s, d, k, &mgrid) != BM_OK) {
+    clear_error();
+    return BM_OK;
+  }
+  if ((st = batch_assign_grid(d, k, sums_lds, &bgrid)) != BM_OK) return st;
+  *handled = true;
+
+  SolverBuffers b;
+  memset(&b.a, 0, sizeof b.a);
+  const int mx_grid = fgrid > mgrid ? fgrid : mgrid;
+  if ((st = prepare_solver(stream, n, s, d, k, T, sp.cand_cap, true, true, true, true, mx_grid, T,
+                           &b)) != BM_OK)
+    return st;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 3; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } evg{ev};
+  for (auto& e : ev) BM_HIP(hipEventCreate(&e));
+  BM_HIP(hipEventRecord(ev[0], stream));
+
+  // (1) every sample, rows (FP32, for reseeding and accumulation) and indices
+  SolverArgs a = b.a;
+  a.X = X;
+  a.n = n;
+  a.s = s;
+  a.d = d;
+  a.k = k;
+  a.x_bf16 = 1;
+  a.T = T;
+  a.seed = seed;
+  a.t0 = o.t_start;
+  a.max_iter = o.max_iter;
+  a.tol = o.tol;
+  a.stop_rule = o.stop_rule;
+  a.trials = o.n_local_trials;
+  a.cmp_rule = BM_CMP_FOPT;
+  a.do_sample = 1;
+  a.do_gather = 1;
+  a.init_incumbent = 1;
+  a.init_forgy = o.init_method == BM_INIT_FORGY ? 1 : 0;
+  a.sums_in_lds = sp.sums_in_lds;
+  a.c64_in_lds = sp.c64_in_lds;
+  a.cand_cap = sp.cand_cap;
+  a.win_lo = sp.win_lo;
+  a.win_hi = sp.win_hi;
+  a.spin_limit = o.spin_limit ? o.spin_limit : kDefaultSpinLimit;
+  a.sample_idx_out = o.sample_idx;
+  const int pmode = g_presample_mode.load();
+  if (pmode != 1) st = launch_presample(a, sp.lds, stream, pmode == 2);
+  if (st == BM_OK) st = launch_solver(a, sp.grid, sp.lds, stream);
+  if (st != BM_OK) return st;
+  if ((st = check_solver_error(a, stream, nullptr)) != BM_OK) return st;
+  float* const Pb = b.a.P;
+  int32_t* const idxb = b.a.idx;
+
+  // (2) the incumbent: the caller's buffer (NaN when fresh)
+  const size_t cbytes = sizeof(float) * static_cast<size_t>(k) * d;
+  std::vector<uint8_t> deg_inc(static_cast<size_t>(k), 1), degw(static_cast<size_t>(k));
+  double f_opt = __builtin_inf();
+  if (o.resume) {
+    memcpy(deg_inc.data(), degenerate, size_t(k));
+    f_opt = o.f_opt_in;
+  } else {
+    BM_HIP(hipMemsetAsync(centroids, 0xFF, cbytes, stream));
+  }
+  std::vector<int32_t> tiles(ntiles, 0);
+  BM_HIP(hipMemcpyAsync(m.tiles, tiles.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, stream));
+  int64_t replaced = 0, passes_total = 0, reseeded = 0, nd = 0;
+  for (int tt = 0; tt < T; ++tt) {
+    const uint32_t t = static_cast<uint32_t>(o.t_start + tt);
+    float* P = Pb + static_cast<size_t>(tt) * s * d;
+    BM_HIP(hipMemcpyAsync(m.cw, centroids, cbytes, hipMemcpyDeviceToDevice, stream));
+    memcpy(degw.data(), deg_inc.data(), size_t(k));
+    BM_HIP(hipMemcpyAsync(m.degw, degw.data(), size_t(k), hipMemcpyHostToDevice, stream));
+    bool any_deg = false;
+    for (int j = 0; j < k; ++j) any_deg = any_deg || degw[j];
+    if (any_deg) {  // reseed on this sample (K-means++ or Forgy, draws of sample t)
+      SolverArgs q = a;
+      q.P = P;
+      q.T = 1;
+      q.t0 = static_cast<int32_t>(t);
+      q.sbatch = 1;
+      q.do_sample = 0;
+      q.do_gather = 0;
+      q.do_seed = 1;
+      q.init_incumbent = 0;
+      q.presampled = 0;
+      q.sample_idx_out = nullptr;
+      q.Cinc = m.cw;
+      q.deg_inc = m.degw;
+      BM_HIP(hipMemsetAsync(b.a.bar, 0, b.ctrl_bytes, stream));
+      if ((st = launch_solver(q, sp.grid, sp.lds, stream)) != BM_OK) return st;
+      int64_t cnt[kNumCounters];
+      BM_HIP(hipMemcpyAsync(cnt, q.counters, sizeof cnt, hipMemcpyDeviceToHost, stream));
+      if ((st = check_solver_error(q, stream, nullptr)) != BM_OK) return st;
+      reseeded += cnt[kCntReseeded];
+      nd += cnt[kCntND];
+    }
+    // (3) K-means on the sample: matrix-core labels, FP64 sums and objective
+    if ((st = launch_gather_rows_bf16(static_cast<const uint16_t*>(X), d,
+                                      idxb + static_cast<size_t>(tt) * s, s, m.p16, stream)) != BM_OK)
+      return st;
+    const float* Pp = P;
+    if (dm != d) {
+      if ((st = launch_pad_rows(P, m.ppad, s, d, stream)) != BM_OK) return st;
+      Pp = m.ppad;
+    }
+    BatchSolve hs;
+    memset(&hs, 0, sizeof hs);
+    hs.row0 = 0;
+    hs.s = s;
+    hs.c0 = 0;
+    hs.k = k;
+    hs.tile0 = 0;
+    hs.ntiles = ntiles;
+    hs.status = kSolveRunning;
+    hs.iter = 1;
+    hs.f_prev = __builtin_inf();
+    BM_HIP(hipMemcpyAsync(m.sv, &hs, sizeof hs, hipMemcpyHostToDevice, stream));
+    BM_HIP(hipMemsetAsync(m.sums, 0, sizeof(double) * static_cast<size_t>(k) * dm, stream));
+    BM_HIP(hipMemsetAsync(m.cnt, 0, sizeof(int32_t) * k, stream));
+    if ((st = launch_batch_init(m.cw, m.c64, m.cpad, k, d, stream)) != BM_OK) return st;
+    int still = 1;
+    for (int round = 0; round <= o.max_iter && still; ++round) {
+      BM_HIP(hipMemsetAsync(m.running, 0, sizeof(int), stream));
+      BM_HIP(hipMemsetAsync(b.done, 0, sizeof(unsigned int), stream));
+      if ((st = launch_assign_mfma(m.p16, s, d, m.cw, m.degw, k, m.lab, nullptr, b.partial, b.done,
+                                   b.sse_dev, b.rechecked, mgrid, stream)) != BM_OK)
+        return st;
+      if ((st = launch_batch_assign(Pp, d, m.cw, m.cpad, m.degw, m.sv, m.tiles, ntiles, kTile, k,
+                                    sums_lds, m.sums, m.cnt, m.tile_f, nullptr, 0, bgrid, stream,
+                                    m.lab)) != BM_OK)
+        return st;
+      if ((st = launch_batch_update(m.sv, 1, m.tile_f, m.sums, m.cnt, m.cw, m.cpad, m.c64, m.degw, d,
+                                    o.max_iter, o.tol, o.stop_rule, m.running, stream)) != BM_OK)
+        return st;
+      BM_HIP(hipMemcpyAsync(&still, m.running, sizeof(int), hipMemcpyDeviceToHost, stream));
+      BM_HIP(hipStreamSynchronize(stream));
+    }
+    if (still) return set_error(BM_EDEVICE, "sample K-means did not finish in max_iter + 1 rounds");
+    BM_HIP(hipMemcpyAsync(&hs, m.sv, sizeof hs, hipMemcpyDeviceToHost, stream));
+    BM_HIP(hipMemcpyAsync(degw.data(), m.degw, size_t(k), hipMemcpyDeviceToHost, stream));
+    BM_HIP(hipStreamSynchronize(stream));
+    if (hs.status != kSolveDone) return set_error(BM_EDEVICE, "sample K-means did not finish");
+    passes_total += hs.passes;
+    nd += hs.nd;
+    if (o.sample_f) o.sample_f[tt] = hs.f;
+    // (4) keep the best (Alg. 1)
+    if (f_opt > hs.f) {
+      BM_HIP(hipMemcpyAsync(centroids, m.cw, cbytes, hipMemcpyDeviceToDevice, stream));
+      memcpy(deg_inc.data(), degw.data(), size_t(k));
+      f_opt = hs.f;
+      ++replaced;
+    }
+  }
+  BM_HIP(hipEventRecord(ev[1], stream));
+  // final assignment (Alg. 1 last step) on the matrix cores
+  double sse_host = 0.0;
+  unsigned long long nrecheck = 0;
+  if (final_pass) {
+    BM_HIP(hipMemcpyAsync(b.a.deg_inc, deg_inc.data(), size_t(k), hipMemcpyHostToDevice, stream));
+    BM_HIP(hipMemsetAsync(b.done, 0, sizeof(unsigned int), stream));
+    BM_HIP(hipMemsetAsync(b.rechecked, 0, sizeof(unsigned long long), stream));
+    if ((st = launch_assign_mfma(static_cast<const uint16_t*>(X), n, d, centroids, b.a.deg_inc, k,
+                                 labels, nullptr, b.partial, b.done, b.sse_dev, b.rechecked, fgrid,
+                                 stream)) != BM_OK)
+      return st;
+    BM_HIP(hipMemcpyAsync(&sse_host, b.sse_dev, sizeof(double), hipMemcpyDeviceToHost, stream));
+    BM_HIP(hipMemcpyAsync(&nrecheck, b.rechecked, sizeof nrecheck, hipMemcpyDeviceToHost, stream));
+  }
+  BM_HIP(hipEventRecord(ev[2], stream));
+  BM_HIP(hipStreamSynchronize(stream));
+  if (sse) *sse = sse_host;
+  if (degenerate) memcpy(degenerate, deg_inc.data(), size_t(k));
+  if (stats) {
+    memset(reinterpret_cast<char*>(stats) + sizeof(uint32_t), 0, sizeof(bm_stats) - sizeof(uint32_t));
+    stats->samples = T;
+    stats->replacements = static_cast<int32_t>(replaced);
+    stats->grid = sp.grid;
+    stats->lloyd_iters = passes_total;
+    stats->reseeded = reseeded;
+    stats->n_d = nd;
+    stats->f_opt = f_opt;
+    stats->ms_solver = elapsed_ms(ev[0], ev[1]);
+    stats->ms_final = final_pass ? elapsed_ms(ev[1], ev[2]) : 0.0;
+    stats->rechecked = static_cast<int64_t>(nrecheck);
+  }
+  return BM_OK;
+}
+
 // The body of bigmeans_fit after validation.  The caller serialises access to
 // the scratch pool in use (the shared pool under g_mu, or a serving slot's own
 // pool).  grid_cap > 0 bounds the cooperative grid.
@@ -702,6 +983,13 @@ bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int
   // Host-side setup and launches of concurrent fits (serving slots) are
   // serialised; the device work they enqueue still overlaps.
   std::unique_lock<std::mutex> launch_lock(g_launch_mu);
+  if (o.precision == BM_PREC_BF16_MFMA && o.x_dtype == BM_BF16 && o.compare_rule == BM_CMP_FOPT &&
+      o.time_budget_ms <= 0.0 && o.final_mode == BM_FINAL_ASSIGN && g_mfma_lloyd.load() && !t_pool) {
+    bool handled = false;
+    st = fit_mfma_run(X, n, d, k, s, n_samples, seed, o, centroids, sse, labels, degenerate, stats,
+                      grid_cap, &handled);
+    if (handled || st != BM_OK) return st;
+  }
   SolverPlan sp;
   if ((st = plan_solver(d, k, s, n, o.grid, &sp)) != BM_OK) return st;
   if (grid_cap > 0 && sp.grid > grid_cap &&

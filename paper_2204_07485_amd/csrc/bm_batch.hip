@@ -42,7 +42,8 @@ __global__ void __launch_bounds__(kBatchBlock)
                         const BatchSolve* __restrict__ sv,
                         const int32_t* __restrict__ tile_solve, int ntiles, int tile_rows,
                         double* __restrict__ sums, int32_t* __restrict__ cnt,
-                        double* __restrict__ tile_f, int32_t* __restrict__ labels, int dry) {
+                        double* __restrict__ tile_f, int32_t* __restrict__ labels, int dry,
+                        const int32_t* __restrict__ labels_in) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int s_k, s_na, s_c0, s_status, s_tile0;
   __shared__ int64_t s_row0, s_s;
@@ -114,7 +115,13 @@ __global__ void __launch_bounds__(kBatchBlock)
       }
       int bj;
       float bd;
-      nearest_f32_sgpr<DM>(x, Cpad + static_cast<size_t>(c0) * DM, act, na, bj, bd);
+      if (labels_in) {
+        // labels computed elsewhere for these centroids (the matrix-core
+        // assignment, which returns the labels of this kernel's FP32 search)
+        bj = labels_in[i];
+      } else {
+        nearest_f32_sgpr<DM>(x, Cpad + static_cast<size_t>(c0) * DM, act, na, bj, bd);
+      }
       if (bj < 0) continue;  // no active centroid: nothing to assign or add
       if (labels && !dry) labels[i] = bj;
       const float* cw = Cl + bj * DM;
@@ -177,6 +184,9 @@ __global__ void __launch_bounds__(kBatchBlock)
   const int k = S->k;
   const int c0 = S->c0;
   if (tid == 0) {
+    int active = 0;  // the slots this round's assignment searched
+    for (int j = 0; j < k; ++j) active += deg[c0 + j] ? 0 : 1;
+    S->nd += S->s * active;
     S->passes += 1;
     int done = 0;
     if (status == kSolveFinal) {
@@ -300,6 +310,20 @@ __global__ void gather_rows_kernel(const void* __restrict__ X, int64_t n, int d,
   }
 }
 
+// Gather BF16 rows of X (bit copies): one wavefront per row; idx is trusted
+// (it comes from the sampler).
+__global__ void gather_rows_bf16_kernel(const uint16_t* __restrict__ X, int d,
+                                        const int32_t* __restrict__ idx, int64_t s,
+                                        uint16_t* __restrict__ P) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t w0 = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int64_t wstride = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  for (int64_t r = w0; r < s; r += wstride) {
+    const int64_t src = idx[r];
+    for (int t = lane; t < d; t += kWave) P[static_cast<size_t>(r) * d + t] = X[static_cast<size_t>(src) * d + t];
+  }
+}
+
 template <int DM, bool SUMS_LDS>
 const void* batch_assign_fn() {
   return reinterpret_cast<const void*>(&batch_assign_kernel<DM, SUMS_LDS>);
@@ -350,13 +374,13 @@ bm_status launch_batch_assign(const float* Pp, int d, const float* C, const floa
                               const uint8_t* deg, const BatchSolve* sv, const int32_t* tile_solve,
                               int ntiles, int tile_rows, int kmax, bool sums_lds, double* sums,
                               int32_t* cnt, double* tile_f, int32_t* labels, int dry, int grid,
-                              hipStream_t stream) {
+                              hipStream_t stream, const int32_t* labels_in) {
   const void* fn = sums_lds ? pick_batch_assign<true>(padded_dim(d)) : pick_batch_assign<false>(padded_dim(d));
   if (!fn || grid < 1) return set_error(BM_EINVAL, "batched assignment: bad plan");
   const size_t lds = batch_assign_lds(d, kmax, sums_lds);
   void* args[] = {const_cast<float**>(&Pp), &d, const_cast<float**>(&C), const_cast<float**>(&Cpad),
                   const_cast<uint8_t**>(&deg), const_cast<BatchSolve**>(&sv), const_cast<int32_t**>(&tile_solve), &ntiles,
-                  &tile_rows, &sums, &cnt, &tile_f, &labels, &dry};
+                  &tile_rows, &sums, &cnt, &tile_f, &labels, &dry, const_cast<int32_t**>(&labels_in)};
   const hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kBatchBlock), args, lds, stream);
   if (e != hipSuccess)
     return set_error(BM_EDEVICE, "batched assignment launch failed: %s", hipGetErrorString(e));
@@ -414,6 +438,18 @@ bm_status launch_gather_rows(const void* X, int x_bf16, int64_t n, int d, const 
                        stream, X, n, d, idx, s, P, bad);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(BM_EDEVICE, "gather launch failed: %s", hipGetErrorString(e));
+  return BM_OK;
+}
+
+bm_status launch_gather_rows_bf16(const uint16_t* X, int d, const int32_t* idx, int64_t s,
+                                  uint16_t* P, hipStream_t stream) {
+  int64_t blocks = (s * kWave + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(gather_rows_bf16_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                     X, d, idx, s, P);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(BM_EDEVICE, "BF16 gather launch failed: %s", hipGetErrorString(e));
   return BM_OK;
 }
 

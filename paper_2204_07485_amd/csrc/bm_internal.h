@@ -181,6 +181,7 @@ struct BatchSolve {
   int32_t status, iter;  // iter: 1-based index of the next assignment
   int32_t passes, pad;
   double f, f_prev;
+  int64_t nd;           // distance evaluations of its assignment passes (s x active slots)
 };
 size_t batch_assign_lds(int d, int kmax, bool sums_lds);
 bm_status batch_assign_grid(int d, int kmax, bool sums_lds, int* grid);
@@ -189,7 +190,10 @@ bm_status launch_batch_assign(const float* Pp, int d, const float* C, const floa
                               const uint8_t* deg, const BatchSolve* sv, const int32_t* tile_solve,
                               int ntiles, int tile_rows, int kmax, bool sums_lds, double* sums,
                               int32_t* cnt, double* tile_f, int32_t* labels, int dry, int grid,
-                              hipStream_t stream);
+                              hipStream_t stream, const int32_t* labels_in = nullptr);
+// P[r] = X[idx[r]] for BF16 rows (bit copies); idx from the sampler.
+bm_status launch_gather_rows_bf16(const uint16_t* X, int d, const int32_t* idx, int64_t s,
+                                  uint16_t* P, hipStream_t stream);
 bm_status launch_batch_update(BatchSolve* sv, int n_solves, const double* tile_f, double* sums,
                               int32_t* cnt, float* C, float* Cpad, double* C64, uint8_t* deg, int d,
                               int max_iter, double tol, int stop_rule, int* running,

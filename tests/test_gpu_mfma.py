@@ -183,3 +183,38 @@ def test_fit_final_pass_mfma():
     np.testing.assert_array_equal(r["labels"].cpu().numpy(), lab.cpu().numpy())
     assert abs(r["sse"] - sse) <= 1e-6 * sse
     assert r["stats"]["rechecked"] >= 0
+
+
+@pytest.mark.parametrize("d,k,init", [(32, 10, 0), (40, 12, 0), (128, 30, 1)])
+def test_fit_sample_lloyd_on_matrix_cores_matches_oracle(d, k, init):
+    # BM_PREC_BF16_MFMA fits run the sample-level K-means on the matrix cores
+    # (labels equal to the FP32 path's); the whole fit must meet the oracle's
+    # bar, and agree with the same fit on the FP32 persistent solver
+    from paper_2204_07485_amd import bigmeans
+    from tests.parity import assert_centroids, assert_labels, assert_sse
+    X, _ = synth.gaussian_mixture(60_000, d, k, seed=13 + d, sigma_range=(0.5, 2.0),
+                                  outlier_frac=0.1)
+    H = synth.to_bf16_bits(X)
+    Hd = torch.from_numpy(H.view(np.int16)).cuda()
+    kw = dict(stop_rule=bigmeans.BM_STOP_REL_OBJ, max_iter=300, init_method=init)
+    print(f"mfma sample lloyd d={d} k={k} init={init}", flush=True)
+    got = bigmeans.bigmeans_fit(Hd, k, 6000, 5, 2, sample_idx=True,
+                                precision=bigmeans.BM_PREC_BF16_MFMA, **kw)
+    prev = bigmeans.debug_mfma_lloyd(0)
+    try:
+        alt = bigmeans.bigmeans_fit(Hd, k, 6000, 5, 2, precision=bigmeans.BM_PREC_BF16_MFMA, **kw)
+    finally:
+        bigmeans.debug_mfma_lloyd(prev)
+    ref = oracle.bigmeans_fit(H, k, 6000, 5, 2, want_sample_idx=True,
+                              stop_rule=oracle.ORC_STOP_REL_OBJ, max_iter=300, init_method=init)
+    Xf = synth.bf16_bits_to_f32(H)
+    assert np.array_equal(got["sample_idx"].cpu().numpy(), ref["sample_idx"])
+    np.testing.assert_allclose(got["sample_f"], ref["sample_f"], rtol=1e-6)
+    np.testing.assert_allclose(got["sample_f"], alt["sample_f"], rtol=1e-6)
+    assert_sse(got["sse"], ref["sse"])
+    assert_sse(got["f_opt"], ref["f_opt"])
+    assert np.array_equal(got["degenerate"], ref["deg"])
+    assert_centroids(got["centroids"].cpu().numpy(), ref["C"], ref["deg"], Xf, ref["labels"])
+    assert_labels(got["labels"].cpu().numpy(), ref["labels"], Xf, ref["C"], ref["deg"])
+    for key in ("samples", "replacements", "reseeded", "lloyd_iters", "n_d"):
+        assert got["stats"][key] == ref["stats"][key], key
