@@ -561,7 +561,7 @@ static bm_status batched_run(int32_t n_solves, const float* P, int32_t d, const 
                                      sums_lds, sums, cnt, tile_f, labels, 0, grid, stream);
   if (cs == BM_OK)
     cs = launch_batch_update(sv_d, n_solves, tile_f, sums, cnt, C, cpad, c64, deg_d, d, o.max_iter,
-                             o.tol, o.stop_rule, running, stream);
+                             o.tol, o.stop_rule, running, stream, kmax);
   const hipError_t ce = hipStreamEndCapture(stream, &graph);
   if (cs != BM_OK) return fail(cs);
   if (ce != hipSuccess)
@@ -714,6 +714,8 @@ struct MfmaLloydBuffers {
   float* cw = nullptr;       // k x d: the sample's centroids
   uint8_t* degw = nullptr;   // k
   int* running = nullptr;
+  double* partials = nullptr;  // ntiles x k x DM (sums in LDS only)
+  int32_t* pcnt = nullptr;     // ntiles x k
 };
 
 // bigmeans_fit for BF16 points with BM_PREC_BF16_MFMA (Alg. 1 with the
@@ -748,8 +750,25 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
     clear_error();
     return BM_OK;
   }
-  constexpr int kTile = 1024;
+  int bgrid = 0;
+  if ((st = batch_assign_grid(d, k, sums_lds, &bgrid)) != BM_OK) return st;
+  // accumulation for the matrix-core labels: a wavefront per row (wide rows)
+  // when its FP64 sums fit in LDS, else the batched kernel; either way one
+  // tile of rows per workgroup, and with the sums in LDS each workgroup writes
+  // one partial block, added in workgroup order
+  const bool wave_rows = labels_accum_lds(d, k) + 1024 <= lds_max;
+  if (wave_rows) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return set_error(BM_EDEVICE, "cannot query the device");
+    const int64_t want = (s + 511) / 512;
+    bgrid = static_cast<int>(want < cus ? (want < 1 ? 1 : want) : cus);
+  }
+  const int64_t tile_rows64 = (s + bgrid - 1) / bgrid;
+  const int kTile = static_cast<int>(tile_rows64);
   const int ntiles = static_cast<int>((s + kTile - 1) / kTile);
+  const bool use_partials = wave_rows || sums_lds;
   // the sample buffers of this form, on the inner pool
   MfmaLloydBuffers m;
   {
@@ -771,18 +790,19 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
       m.cw = L.take<float>(static_cast<size_t>(k) * d);
       m.degw = L.take<uint8_t>(k);
       m.running = L.take<int>(1);
+      m.partials = L.take<double>(use_partials ? static_cast<size_t>(bgrid) * k * dm : 1);
+      m.pcnt = L.take<int32_t>(use_partials ? static_cast<size_t>(bgrid) * k : 1);
       if (round == 0) {
         base = static_cast<char*>(scratch_get(L.off + 256, stream, &st));
         if (!base) return st;
       }
     }
   }
-  int mgrid = 0, bgrid = 0;
+  int mgrid = 0;
   if (plan_assign_mfma(m.p16, s, d, k, &mgrid) != BM_OK) {
     clear_error();
     return BM_OK;
   }
-  if ((st = batch_assign_grid(d, k, sums_lds, &bgrid)) != BM_OK) return st;
   *handled = true;
 
   SolverBuffers b;
@@ -829,11 +849,18 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
   a.win_hi = sp.win_hi;
   a.spin_limit = o.spin_limit ? o.spin_limit : kDefaultSpinLimit;
   a.sample_idx_out = o.sample_idx;
+  using clk = std::chrono::steady_clock;
+  auto since = [](clk::time_point t0) {
+    return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  };
+  double ms_sampling = 0.0, ms_seeding = 0.0, ms_lloyd = 0.0;
+  auto tp = clk::now();
   const int pmode = g_presample_mode.load();
   if (pmode != 1) st = launch_presample(a, sp.lds, stream, pmode == 2);
   if (st == BM_OK) st = launch_solver(a, sp.grid, sp.lds, stream);
   if (st != BM_OK) return st;
   if ((st = check_solver_error(a, stream, nullptr)) != BM_OK) return st;
+  ms_sampling += since(tp);
   float* const Pb = b.a.P;
   int32_t* const idxb = b.a.idx;
 
@@ -859,6 +886,7 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
     bool any_deg = false;
     for (int j = 0; j < k; ++j) any_deg = any_deg || degw[j];
     if (any_deg) {  // reseed on this sample (K-means++ or Forgy, draws of sample t)
+      tp = clk::now();
       SolverArgs q = a;
       q.P = P;
       q.T = 1;
@@ -879,13 +907,15 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
       if ((st = check_solver_error(q, stream, nullptr)) != BM_OK) return st;
       reseeded += cnt[kCntReseeded];
       nd += cnt[kCntND];
+      ms_seeding += since(tp);
     }
     // (3) K-means on the sample: matrix-core labels, FP64 sums and objective
+    tp = clk::now();
     if ((st = launch_gather_rows_bf16(static_cast<const uint16_t*>(X), d,
                                       idxb + static_cast<size_t>(tt) * s, s, m.p16, stream)) != BM_OK)
       return st;
     const float* Pp = P;
-    if (dm != d) {
+    if (dm != d && !wave_rows) {
       if ((st = launch_pad_rows(P, m.ppad, s, d, stream)) != BM_OK) return st;
       Pp = m.ppad;
     }
@@ -904,28 +934,46 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
     BM_HIP(hipMemsetAsync(m.sums, 0, sizeof(double) * static_cast<size_t>(k) * dm, stream));
     BM_HIP(hipMemsetAsync(m.cnt, 0, sizeof(int32_t) * k, stream));
     if ((st = launch_batch_init(m.cw, m.c64, m.cpad, k, d, stream)) != BM_OK) return st;
+    // Rounds go out in groups of kRoundsPerSync between reads of the solve's
+    // status: every kernel of a round returns at once when the solve is done,
+    // so rounds queued past the end cost a few empty launches, less than a
+    // host round trip per round.
+    constexpr int kRoundsPerSync = 4;
     int still = 1;
-    for (int round = 0; round <= o.max_iter && still; ++round) {
-      BM_HIP(hipMemsetAsync(m.running, 0, sizeof(int), stream));
-      BM_HIP(hipMemsetAsync(b.done, 0, sizeof(unsigned int), stream));
-      if ((st = launch_assign_mfma(m.p16, s, d, m.cw, m.degw, k, m.lab, nullptr, b.partial, b.done,
-                                   b.sse_dev, b.rechecked, mgrid, stream)) != BM_OK)
-        return st;
-      if ((st = launch_batch_assign(Pp, d, m.cw, m.cpad, m.degw, m.sv, m.tiles, ntiles, kTile, k,
-                                    sums_lds, m.sums, m.cnt, m.tile_f, nullptr, 0, bgrid, stream,
-                                    m.lab)) != BM_OK)
-        return st;
-      if ((st = launch_batch_update(m.sv, 1, m.tile_f, m.sums, m.cnt, m.cw, m.cpad, m.c64, m.degw, d,
-                                    o.max_iter, o.tol, o.stop_rule, m.running, stream)) != BM_OK)
-        return st;
-      BM_HIP(hipMemcpyAsync(&still, m.running, sizeof(int), hipMemcpyDeviceToHost, stream));
+    for (int round = 0; round <= o.max_iter && still;) {
+      for (int q = 0; q < kRoundsPerSync && round <= o.max_iter; ++q, ++round) {
+        if ((st = launch_assign_mfma(m.p16, s, d, m.cw, m.degw, k, m.lab, nullptr, nullptr, nullptr,
+                                     nullptr, b.rechecked, mgrid, stream, &m.sv->status)) != BM_OK)
+          return st;
+        if (wave_rows) {
+          if ((st = launch_labels_accum(m.p16, s, d, k, m.cw, m.lab, m.sv, m.partials, m.pcnt,
+                                        m.tile_f, ntiles, stream)) != BM_OK)
+            return st;
+        } else if ((st = launch_batch_assign(Pp, d, m.cw, m.cpad, m.degw, m.sv, m.tiles, ntiles, kTile,
+                                             k, sums_lds, m.sums, m.cnt, m.tile_f, nullptr, 0, ntiles,
+                                             stream, m.lab, sums_lds ? m.partials : nullptr,
+                                             sums_lds ? m.pcnt : nullptr)) != BM_OK) {
+          return st;
+        }
+        if (use_partials &&
+            (st = launch_batch_reduce(m.partials, m.pcnt, ntiles, k, d, m.sums, m.cnt, m.sv, stream)) != BM_OK)
+          return st;
+        if ((st = launch_batch_update(m.sv, 1, m.tile_f, m.sums, m.cnt, m.cw, m.cpad, m.c64, m.degw, d,
+                                      o.max_iter, o.tol, o.stop_rule, m.running, stream, k)) != BM_OK)
+          return st;
+      }
+      // the solve's status after these rounds
+      int32_t status = kSolveRunning;
+      BM_HIP(hipMemcpyAsync(&status, &m.sv->status, sizeof status, hipMemcpyDeviceToHost, stream));
       BM_HIP(hipStreamSynchronize(stream));
+      still = status != kSolveDone;
     }
     if (still) return set_error(BM_EDEVICE, "sample K-means did not finish in max_iter + 1 rounds");
     BM_HIP(hipMemcpyAsync(&hs, m.sv, sizeof hs, hipMemcpyDeviceToHost, stream));
     BM_HIP(hipMemcpyAsync(degw.data(), m.degw, size_t(k), hipMemcpyDeviceToHost, stream));
     BM_HIP(hipStreamSynchronize(stream));
     if (hs.status != kSolveDone) return set_error(BM_EDEVICE, "sample K-means did not finish");
+    ms_lloyd += since(tp);
     passes_total += hs.passes;
     nd += hs.nd;
     if (o.sample_f) o.sample_f[tt] = hs.f;
@@ -968,6 +1016,10 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
     stats->ms_solver = elapsed_ms(ev[0], ev[1]);
     stats->ms_final = final_pass ? elapsed_ms(ev[1], ev[2]) : 0.0;
     stats->rechecked = static_cast<int64_t>(nrecheck);
+    // host-timed phases of this form (each ends with a synchronisation)
+    stats->ms_sampling = ms_sampling;
+    stats->ms_seeding = ms_seeding;
+    stats->ms_lloyd = ms_lloyd;
   }
   return BM_OK;
 }

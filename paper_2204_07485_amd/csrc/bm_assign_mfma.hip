@@ -203,7 +203,9 @@ __global__ void __launch_bounds__((block_for<KS, VEC>()))
                        const float* __restrict__ C, const uint8_t* __restrict__ deg, int k,
                        int32_t* __restrict__ labels, float* __restrict__ min_d2,
                        double* __restrict__ partial, unsigned int* __restrict__ done,
-                       double* __restrict__ sse_out, unsigned long long* __restrict__ rechecked) {
+                       double* __restrict__ sse_out, unsigned long long* __restrict__ rechecked,
+                       const int32_t* __restrict__ stop) {
+  if (stop && *stop == kSolveDone) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const MfmaLds P = mfma_lds_plan(KS, k);
   const int CT = P.ct;
@@ -435,6 +437,7 @@ __global__ void __launch_bounds__((block_for<KS, VEC>()))
     }
   }
   if (rechecked && nrecheck) atomicAdd(rechecked, nrecheck);
+  if (!partial) return;
   const double bsum = block_sum_f64<kMfmaBlock>(sse, s_tmp);
   if (tid == 0) {
     partial[blockIdx.x] = bsum;
@@ -518,7 +521,8 @@ bm_status plan_assign_mfma(const void* X, int64_t n, int d, int k, int* grid) {
 bm_status launch_assign_mfma(const uint16_t* X, int64_t n, int d, const float* C,
                              const uint8_t* deg_dev, int k, int32_t* labels, float* min_d2,
                              double* partial, unsigned int* done, double* sse_dev,
-                             unsigned long long* rechecked, int grid, hipStream_t stream) {
+                             unsigned long long* rechecked, int grid, hipStream_t stream,
+                             const int32_t* stop) {
   const int ks = mfma_ks(d);
   if (grid < 1 || n < 1 || d < 1 || d > 256 || k < 1 || k > 16 * kMaxCT)
     return set_error(BM_EINVAL, "MFMA assignment: bad plan");
@@ -526,7 +530,7 @@ bm_status launch_assign_mfma(const uint16_t* X, int64_t n, int d, const float* C
   const size_t lds = mfma_lds_plan(ks, k).total;
   void* args[] = {const_cast<uint16_t**>(&X), &n, &d, const_cast<float**>(&C),
                   const_cast<uint8_t**>(&deg_dev), &k, &labels, &min_d2, &partial, &done,
-                  &sse_dev, &rechecked};
+                  &sse_dev, &rechecked, const_cast<int32_t**>(&stop)};
   const hipError_t e =
       hipLaunchKernel(fn, dim3(grid), dim3(mfma_block(ks, mfma_vec(X, d))), args, lds, stream);
   if (e != hipSuccess)

@@ -190,14 +190,27 @@ bm_status launch_batch_assign(const float* Pp, int d, const float* C, const floa
                               const uint8_t* deg, const BatchSolve* sv, const int32_t* tile_solve,
                               int ntiles, int tile_rows, int kmax, bool sums_lds, double* sums,
                               int32_t* cnt, double* tile_f, int32_t* labels, int dry, int grid,
-                              hipStream_t stream, const int32_t* labels_in = nullptr);
+                              hipStream_t stream, const int32_t* labels_in = nullptr,
+                              double* partials = nullptr, int32_t* pcnt = nullptr);
+// One solve (sv[0]) accumulated as per-workgroup partial blocks (partials:
+// grid x k x DM, pcnt: grid x k, from launch_batch_assign): sums and counts
+// added in workgroup order.
+bm_status launch_batch_reduce(const double* partials, const int32_t* pcnt, int nparts, int k, int d,
+                              double* sums, int32_t* cnt, const BatchSolve* sv, hipStream_t stream);
+// One solve (sv[0]) with labels given: FP64 sums, counts (partial blocks,
+// grid x k x DM and grid x k) and the objective partials (tile_f, grid) of
+// d-wide BF16 rows (grid <= s workgroups, each a contiguous range of rows).
+size_t labels_accum_lds(int d, int k);
+bm_status launch_labels_accum(const uint16_t* P, int64_t s, int d, int k, const float* C,
+                              const int32_t* labels, const BatchSolve* sv, double* partials,
+                              int32_t* pcnt, double* tile_f, int grid, hipStream_t stream);
 // P[r] = X[idx[r]] for BF16 rows (bit copies); idx from the sampler.
 bm_status launch_gather_rows_bf16(const uint16_t* X, int d, const int32_t* idx, int64_t s,
                                   uint16_t* P, hipStream_t stream);
 bm_status launch_batch_update(BatchSolve* sv, int n_solves, const double* tile_f, double* sums,
                               int32_t* cnt, float* C, float* Cpad, double* C64, uint8_t* deg, int d,
                               int max_iter, double tol, int stop_rule, int* running,
-                              hipStream_t stream);
+                              hipStream_t stream, int kmax);
 bm_status launch_batch_init(const float* C, double* C64, float* Cpad, int64_t rows, int d,
                             hipStream_t stream);
 bm_status launch_pad_rows(const float* P, float* Pp, int64_t rows, int d, hipStream_t stream);
@@ -208,9 +221,12 @@ bm_status launch_gather_rows(const void* X, int x_bf16, int64_t n, int d, const 
 // picks the grid; the launch writes the same outputs as launch_assign and
 // adds the number of points it recomputed on the FP32 path to *rechecked.
 bm_status plan_assign_mfma(const void* X, int64_t n, int d, int k, int* grid);
+// With `stop` (a solve's status word) the launch does nothing once the solve
+// is done; partial == nullptr leaves the objective out (labels only).
 bm_status launch_assign_mfma(const uint16_t* X, int64_t n, int d, const float* C,
                              const uint8_t* deg_dev, int k, int32_t* labels, float* min_d2,
                              double* partial, unsigned int* done, double* sse_dev,
-                             unsigned long long* rechecked, int grid, hipStream_t stream);
+                             unsigned long long* rechecked, int grid, hipStream_t stream,
+                             const int32_t* stop = nullptr);
 
 }  // namespace bm

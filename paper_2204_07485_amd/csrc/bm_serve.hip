@@ -455,7 +455,7 @@ bm_status arena_round(Arena& A, hipStream_t stream) {
                                      A.sums_lds, A.sums, A.cnt, A.tile_f, nullptr, 0, A.grid, stream);
   if (st != BM_OK) return st;
   st = launch_batch_update(A.sv, A.nslot, A.tile_f, A.sums, A.cnt, A.C, A.Cpad, A.c64, A.deg, A.d,
-                           A.key.max_iter, A.key.tol, A.key.stop_rule, A.running, stream);
+                           A.key.max_iter, A.key.tol, A.key.stop_rule, A.running, stream, A.kmax);
   if (st != BM_OK) return st;
   BM_HIPR(hipMemcpyAsync(A.hs.data(), A.sv, sizeof(BatchSolve) * A.nslot, hipMemcpyDeviceToHost, stream));
   return BM_OK;

@@ -1520,6 +1520,33 @@ __global__ void __launch_bounds__(kBlock) presample_emit_kernel(SolverArgs a, in
   emit_sample<DM>(a, slot_bufs(a, a.P, a.idx, b), L, static_cast<uint32_t>(a.t0 + b), b, p0, p1, g);
 }
 
+// Rows of every presampled sample (wide rows): one wavefront per row, lanes
+// over the coordinates, so reads and writes are coalesced; the emit pass then
+// writes only the indices.  Nothing is done after a predicted-window miss (the
+// solver draws and gathers the samples itself).
+template <bool BF16>
+__global__ void __launch_bounds__(kBlock) presample_gather_kernel(SolverArgs a) {
+  if (__hip_atomic_load(a.presample_miss, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t rows = static_cast<int64_t>(a.T) * a.s;
+  const int64_t w0 = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave;
+  const int64_t wstride = static_cast<int64_t>(gridDim.x) * kBlock / kWave;
+  const int d = a.d;
+  for (int64_t r = w0; r < rows; r += wstride) {
+    const int64_t src = a.idx[r];
+    if (src < 0 || src >= a.n) continue;  // never read outside X
+    float* dst = a.P + static_cast<size_t>(r) * d;
+    for (int t = lane; t < d; t += kWave) {
+      float v;
+      if (BF16)
+        v = bf16_bits_to_float(static_cast<const uint16_t*>(a.X)[static_cast<size_t>(src) * d + t]);
+      else
+        v = static_cast<const float*>(a.X)[static_cast<size_t>(src) * d + t];
+      dst[t] = v;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 
@@ -1640,12 +1667,24 @@ bm_status launch_presample(SolverArgs& a, size_t lds, hipStream_t stream, bool f
         return set_error(BM_ENOTSUP, "cannot reserve %zu B of LDS for presampling", lds);
   }
   SolverArgs copy = a;
+  // wide rows are gathered by a separate coalesced pass after the emit
+  const bool coop_gather = a.do_gather && a.d >= 32 && a.P && a.idx;
+  if (coop_gather) copy.do_gather = 0;
   int g32 = static_cast<int>(gp);
   void* args[] = {&copy, &g32};
   hipError_t e = hipLaunchKernel(fc, dim3(g32, a.T), dim3(kBlock), args, lds, stream);
   if (e == hipSuccess) e = hipLaunchKernel(fs, dim3(a.T), dim3(kBlock), args, lds, stream);
   if (e == hipSuccess && force_miss) e = hipMemsetAsync(a.presample_miss, 1, 1, stream);  // test hook
   if (e == hipSuccess) e = hipLaunchKernel(fe, dim3(g32, a.T), dim3(kBlock), args, lds, stream);
+  if (e == hipSuccess && coop_gather) {
+    const int64_t rows = static_cast<int64_t>(a.T) * a.s;
+    int64_t blocks = (rows * kWave + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    void* gargs[] = {&copy};
+    const void* fg = a.x_bf16 ? reinterpret_cast<const void*>(&presample_gather_kernel<true>)
+                              : reinterpret_cast<const void*>(&presample_gather_kernel<false>);
+    e = hipLaunchKernel(fg, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), gargs, 0, stream);
+  }
   if (e != hipSuccess) return set_error(BM_EDEVICE, "presample launch failed: %s", hipGetErrorString(e));
   a.presampled = 1;
   return BM_OK;
