@@ -572,7 +572,8 @@ def debug_counters():
              6: "select_passes", 8: "ticks_sample", 9: "ticks_seed", 10: "ticks_lloyd",
              11: "ticks_pass", 12: "ticks_post", 13: "ticks_barrier", 14: "ticks_collect",
              15: "ticks_collect_wait", 16: "ticks_select", 17: "ticks_emit", 18: "ticks_assign",
-             19: "ticks_flush"}
+             19: "ticks_flush", 20: "ticks_seed_init", 21: "ticks_seed_locate",
+             22: "ticks_seed_pot", 23: "ticks_seed_update"}
     return {v: int(out[k]) for k, v in names.items()}
 
 

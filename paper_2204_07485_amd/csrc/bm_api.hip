@@ -329,11 +329,7 @@ static bm_status prepare_solver(hipStream_t stream, int64_t n, int64_t s, int d,
   return BM_OK;
 }
 
-static bm_status check_solver_error(const SolverArgs& a, hipStream_t stream, int32_t* code_out) {
-  int32_t code = 0;
-  BM_HIP(hipMemcpyAsync(&code, a.err, sizeof code, hipMemcpyDeviceToHost, stream));
-  BM_HIP(hipStreamSynchronize(stream));
-  if (code_out) *code_out = code;
+static bm_status solver_error(int32_t code) {
   switch (code) {
     case kErrNone: return BM_OK;
     case kErrBarrier:
@@ -342,6 +338,14 @@ static bm_status check_solver_error(const SolverArgs& a, hipStream_t stream, int
     case kErrSeed: return set_error(BM_EDEVICE, "solver aborted: K-means++ found no candidate");
     default: return set_error(BM_EDEVICE, "solver aborted with code %d", code);
   }
+}
+
+static bm_status check_solver_error(const SolverArgs& a, hipStream_t stream, int32_t* code_out) {
+  int32_t code = 0;
+  BM_HIP(hipMemcpyAsync(&code, a.err, sizeof code, hipMemcpyDeviceToHost, stream));
+  BM_HIP(hipStreamSynchronize(stream));
+  if (code_out) *code_out = code;
+  return solver_error(code);
 }
 
 static bm_status check_sizes(int64_t n, int d, int k, int64_t s) {
@@ -700,10 +704,36 @@ size_t fit_scratch_bytes(int64_t n, int32_t d, int32_t k, int64_t s, int32_t n_s
 }
 
 // Device buffers of the matrix-core sample K-means (one problem at a time).
+// Pinned host memory for the small per-sample transfers of the matrix-core
+// fit, so they queue behind the kernels instead of stalling the host; one
+// block per thread, kept until the process ends.
+struct MfmaStage {
+  BatchSolve hs;                // the solve record after a group of rounds
+  int64_t cnt[kNumCounters];    // reseeding counters
+  int32_t err;                  // reseeding error code
+  int32_t pad;
+  uint8_t deg[256];             // the working flags after a group of rounds (k <= 256)
+};
+static thread_local MfmaStage* t_mfma_stage = nullptr;
+
+static bm_status mfma_stage(MfmaStage** out) {
+  if (!t_mfma_stage) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sizeof(MfmaStage), hipHostMallocDefault) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return set_error(BM_ENOMEM, "cannot allocate pinned host staging");
+    }
+    t_mfma_stage = static_cast<MfmaStage*>(p);
+  }
+  *out = t_mfma_stage;
+  return BM_OK;
+}
+
 struct MfmaLloydBuffers {
   uint16_t* p16 = nullptr;   // s x d BF16 rows of the sample
   float* ppad = nullptr;     // s x DM FP32 rows when d != DM
   int32_t* lab = nullptr;    // s labels from the matrix cores
+  int* bad = nullptr;        // set by the FP32 row gather on an index outside X
   BatchSolve* sv = nullptr;
   int32_t* tiles = nullptr;
   double* tile_f = nullptr;
@@ -713,6 +743,7 @@ struct MfmaLloydBuffers {
   float* cpad = nullptr;     // k x DM
   float* cw = nullptr;       // k x d: the sample's centroids
   uint8_t* degw = nullptr;   // k
+  uint8_t* deginc = nullptr; // k: the incumbent's degenerate flags
   int* running = nullptr;
   double* partials = nullptr;  // ntiles x k x DM (sums in LDS only)
   int32_t* pcnt = nullptr;     // ntiles x k
@@ -789,7 +820,9 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
       m.cpad = L.take<float>(static_cast<size_t>(k) * dm);
       m.cw = L.take<float>(static_cast<size_t>(k) * d);
       m.degw = L.take<uint8_t>(k);
+      m.deginc = L.take<uint8_t>(k);
       m.running = L.take<int>(1);
+      m.bad = L.take<int>(1);
       m.partials = L.take<double>(use_partials ? static_cast<size_t>(bgrid) * k * dm : 1);
       m.pcnt = L.take<int32_t>(use_partials ? static_cast<size_t>(bgrid) * k : 1);
       if (round == 0) {
@@ -822,7 +855,8 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
   for (auto& e : ev) BM_HIP(hipEventCreate(&e));
   BM_HIP(hipEventRecord(ev[0], stream));
 
-  // (1) every sample, rows (FP32, for reseeding and accumulation) and indices
+  // (1) every sample's indices; FP32 rows too when the accumulation reads them
+  // (otherwise a sample's FP32 rows are gathered only when it reseeds)
   SolverArgs a = b.a;
   a.X = X;
   a.n = n;
@@ -839,7 +873,7 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
   a.trials = o.n_local_trials;
   a.cmp_rule = BM_CMP_FOPT;
   a.do_sample = 1;
-  a.do_gather = 1;
+  a.do_gather = wave_rows ? 0 : 1;
   a.init_incumbent = 1;
   a.init_forgy = o.init_method == BM_INIT_FORGY ? 1 : 0;
   a.sums_in_lds = sp.sums_in_lds;
@@ -866,7 +900,7 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
 
   // (2) the incumbent: the caller's buffer (NaN when fresh)
   const size_t cbytes = sizeof(float) * static_cast<size_t>(k) * d;
-  std::vector<uint8_t> deg_inc(static_cast<size_t>(k), 1), degw(static_cast<size_t>(k));
+  std::vector<uint8_t> deg_inc(static_cast<size_t>(k), 1);
   double f_opt = __builtin_inf();
   if (o.resume) {
     memcpy(deg_inc.data(), degenerate, size_t(k));
@@ -874,19 +908,46 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
   } else {
     BM_HIP(hipMemsetAsync(centroids, 0xFF, cbytes, stream));
   }
+  MfmaStage* stg = nullptr;
+  if (k > 256) return set_error(BM_EINVAL, "k = %d beyond the matrix-core fit's 256", k);
+  if ((st = mfma_stage(&stg)) != BM_OK) return st;
+  BM_HIP(hipMemcpyAsync(m.deginc, deg_inc.data(), size_t(k), hipMemcpyHostToDevice, stream));
   std::vector<int32_t> tiles(ntiles, 0);
   BM_HIP(hipMemcpyAsync(m.tiles, tiles.data(), sizeof(int32_t) * ntiles, hipMemcpyHostToDevice, stream));
   int64_t replaced = 0, passes_total = 0, reseeded = 0, nd = 0;
+  int64_t seed_counters[kNumCounters] = {};
+  // per-sample phase boundaries on the stream: start, seeded, last round
+  hipEvent_t pe[3] = {nullptr, nullptr, nullptr};
+  EvGuard peg{pe};
+  for (auto& e : pe) BM_HIP(hipEventCreate(&e));
+  BatchSolve init;
+  memset(&init, 0, sizeof init);
+  init.row0 = 0;
+  init.s = s;
+  init.c0 = 0;
+  init.k = k;
+  init.tile0 = 0;
+  init.ntiles = ntiles;
+  init.status = kSolveRunning;
+  init.iter = 1;
+  init.f_prev = __builtin_inf();
   for (int tt = 0; tt < T; ++tt) {
     const uint32_t t = static_cast<uint32_t>(o.t_start + tt);
     float* P = Pb + static_cast<size_t>(tt) * s * d;
-    BM_HIP(hipMemcpyAsync(m.cw, centroids, cbytes, hipMemcpyDeviceToDevice, stream));
-    memcpy(degw.data(), deg_inc.data(), size_t(k));
-    BM_HIP(hipMemcpyAsync(m.degw, degw.data(), size_t(k), hipMemcpyHostToDevice, stream));
+    BM_HIP(hipEventRecord(pe[0], stream));
+    // the sample's solve starts from the incumbent
+    if ((st = launch_solve_start(centroids, m.deginc, m.cw, m.degw, m.sv, init, m.sums, m.cnt, k, d,
+                                 stream)) != BM_OK)
+      return st;
     bool any_deg = false;
-    for (int j = 0; j < k; ++j) any_deg = any_deg || degw[j];
+    for (int j = 0; j < k; ++j) any_deg = any_deg || deg_inc[j];
     if (any_deg) {  // reseed on this sample (K-means++ or Forgy, draws of sample t)
-      tp = clk::now();
+      if (wave_rows) {
+        BM_HIP(hipMemsetAsync(m.bad, 0, sizeof(int), stream));
+        if ((st = launch_gather_rows(X, 1, n, d, idxb + static_cast<size_t>(tt) * s, s, P, m.bad,
+                                     stream)) != BM_OK)
+          return st;
+      }
       SolverArgs q = a;
       q.P = P;
       q.T = 1;
@@ -902,15 +963,11 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
       q.deg_inc = m.degw;
       BM_HIP(hipMemsetAsync(b.a.bar, 0, b.ctrl_bytes, stream));
       if ((st = launch_solver(q, sp.grid, sp.lds, stream)) != BM_OK) return st;
-      int64_t cnt[kNumCounters];
-      BM_HIP(hipMemcpyAsync(cnt, q.counters, sizeof cnt, hipMemcpyDeviceToHost, stream));
-      if ((st = check_solver_error(q, stream, nullptr)) != BM_OK) return st;
-      reseeded += cnt[kCntReseeded];
-      nd += cnt[kCntND];
-      ms_seeding += since(tp);
+      BM_HIP(hipMemcpyAsync(stg->cnt, q.counters, sizeof stg->cnt, hipMemcpyDeviceToHost, stream));
+      BM_HIP(hipMemcpyAsync(&stg->err, q.err, sizeof stg->err, hipMemcpyDeviceToHost, stream));
     }
+    BM_HIP(hipEventRecord(pe[1], stream));
     // (3) K-means on the sample: matrix-core labels, FP64 sums and objective
-    tp = clk::now();
     if ((st = launch_gather_rows_bf16(static_cast<const uint16_t*>(X), d,
                                       idxb + static_cast<size_t>(tt) * s, s, m.p16, stream)) != BM_OK)
       return st;
@@ -919,28 +976,14 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
       if ((st = launch_pad_rows(P, m.ppad, s, d, stream)) != BM_OK) return st;
       Pp = m.ppad;
     }
-    BatchSolve hs;
-    memset(&hs, 0, sizeof hs);
-    hs.row0 = 0;
-    hs.s = s;
-    hs.c0 = 0;
-    hs.k = k;
-    hs.tile0 = 0;
-    hs.ntiles = ntiles;
-    hs.status = kSolveRunning;
-    hs.iter = 1;
-    hs.f_prev = __builtin_inf();
-    BM_HIP(hipMemcpyAsync(m.sv, &hs, sizeof hs, hipMemcpyHostToDevice, stream));
-    BM_HIP(hipMemsetAsync(m.sums, 0, sizeof(double) * static_cast<size_t>(k) * dm, stream));
-    BM_HIP(hipMemsetAsync(m.cnt, 0, sizeof(int32_t) * k, stream));
     if ((st = launch_batch_init(m.cw, m.c64, m.cpad, k, d, stream)) != BM_OK) return st;
     // Rounds go out in groups of kRoundsPerSync between reads of the solve's
-    // status: every kernel of a round returns at once when the solve is done,
+    // record: every kernel of a round returns at once when the solve is done,
     // so rounds queued past the end cost a few empty launches, less than a
     // host round trip per round.
     constexpr int kRoundsPerSync = 4;
-    int still = 1;
-    for (int round = 0; round <= o.max_iter && still;) {
+    bool done = false, first_group = true;
+    for (int round = 0; round <= o.max_iter && !done;) {
       for (int q = 0; q < kRoundsPerSync && round <= o.max_iter; ++q, ++round) {
         if ((st = launch_assign_mfma(m.p16, s, d, m.cw, m.degw, k, m.lab, nullptr, nullptr, nullptr,
                                      nullptr, b.rechecked, mgrid, stream, &m.sv->status)) != BM_OK)
@@ -962,25 +1005,32 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
                                       o.max_iter, o.tol, o.stop_rule, m.running, stream, k)) != BM_OK)
           return st;
       }
-      // the solve's status after these rounds
-      int32_t status = kSolveRunning;
-      BM_HIP(hipMemcpyAsync(&status, &m.sv->status, sizeof status, hipMemcpyDeviceToHost, stream));
+      // the solve's record and flags after these rounds
+      BM_HIP(hipEventRecord(pe[2], stream));
+      BM_HIP(hipMemcpyAsync(&stg->hs, m.sv, sizeof stg->hs, hipMemcpyDeviceToHost, stream));
+      BM_HIP(hipMemcpyAsync(stg->deg, m.degw, size_t(k), hipMemcpyDeviceToHost, stream));
       BM_HIP(hipStreamSynchronize(stream));
-      still = status != kSolveDone;
+      if (first_group && any_deg) {
+        if ((st = solver_error(stg->err)) != BM_OK) return st;
+        reseeded += stg->cnt[kCntReseeded];
+        nd += stg->cnt[kCntND];
+        for (int c = 0; c < kNumCounters; ++c) seed_counters[c] += stg->cnt[c];
+      }
+      first_group = false;
+      done = stg->hs.status == kSolveDone;
     }
-    if (still) return set_error(BM_EDEVICE, "sample K-means did not finish in max_iter + 1 rounds");
-    BM_HIP(hipMemcpyAsync(&hs, m.sv, sizeof hs, hipMemcpyDeviceToHost, stream));
-    BM_HIP(hipMemcpyAsync(degw.data(), m.degw, size_t(k), hipMemcpyDeviceToHost, stream));
-    BM_HIP(hipStreamSynchronize(stream));
-    if (hs.status != kSolveDone) return set_error(BM_EDEVICE, "sample K-means did not finish");
-    ms_lloyd += since(tp);
+    if (!done) return set_error(BM_EDEVICE, "sample K-means did not finish in max_iter + 1 rounds");
+    const BatchSolve hs = stg->hs;
+    if (any_deg) ms_seeding += elapsed_ms(pe[0], pe[1]);
+    ms_lloyd += elapsed_ms(pe[1], pe[2]);
     passes_total += hs.passes;
     nd += hs.nd;
     if (o.sample_f) o.sample_f[tt] = hs.f;
     // (4) keep the best (Alg. 1)
     if (f_opt > hs.f) {
       BM_HIP(hipMemcpyAsync(centroids, m.cw, cbytes, hipMemcpyDeviceToDevice, stream));
-      memcpy(deg_inc.data(), degw.data(), size_t(k));
+      BM_HIP(hipMemcpyAsync(m.deginc, m.degw, size_t(k), hipMemcpyDeviceToDevice, stream));
+      memcpy(deg_inc.data(), stg->deg, size_t(k));
       f_opt = hs.f;
       ++replaced;
     }
@@ -1004,6 +1054,9 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
   BM_HIP(hipStreamSynchronize(stream));
   if (sse) *sse = sse_host;
   if (degenerate) memcpy(degenerate, deg_inc.data(), size_t(k));
+  seed_counters[kCntPasses] = passes_total;
+  seed_counters[kCntSamples] = T;
+  memcpy(g_last_counters, seed_counters, sizeof seed_counters);
   if (stats) {
     memset(reinterpret_cast<char*>(stats) + sizeof(uint32_t), 0, sizeof(bm_stats) - sizeof(uint32_t));
     stats->samples = T;

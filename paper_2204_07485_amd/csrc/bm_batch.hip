@@ -575,6 +575,25 @@ __global__ void batch_init_kernel(const float* __restrict__ C, double* __restric
   }
 }
 
+// Start of one solve (the matrix-core fit's sample): working centroids and
+// flags from the incumbent, the solve record, cleared sums and counts; one
+// launch in place of a copy, two transfers and two fills.
+__global__ void solve_start_kernel(const float* __restrict__ Cinc, const uint8_t* __restrict__ deginc,
+                                   float* __restrict__ cw, uint8_t* __restrict__ degw,
+                                   BatchSolve* __restrict__ sv, BatchSolve init,
+                                   double* __restrict__ sums, int32_t* __restrict__ cnt, int k, int d,
+                                   int dm) {
+  const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t e = tid; e < static_cast<int64_t>(k) * d; e += stride) cw[e] = Cinc[e];
+  for (int64_t e = tid; e < static_cast<int64_t>(k) * dm; e += stride) sums[e] = 0.0;
+  for (int64_t j = tid; j < k; j += stride) {
+    degw[j] = deginc[j];
+    cnt[j] = 0;
+  }
+  if (tid == 0) *sv = init;
+}
+
 // Copy rows (d wide) into rows DM wide, zero padded.
 __global__ void pad_rows_kernel(const float* __restrict__ P, float* __restrict__ Pp, int64_t rows,
                                 int d, int dm) {
@@ -736,6 +755,20 @@ bm_status launch_batch_init(const float* C, double* C64, float* Cpad, int64_t ro
                      dim3(256), 0, stream, C, C64, Cpad, rows, d, dm);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(BM_EDEVICE, "batch init launch failed: %s", hipGetErrorString(e));
+  return BM_OK;
+}
+
+bm_status launch_solve_start(const float* Cinc, const uint8_t* deginc, float* cw, uint8_t* degw,
+                             BatchSolve* sv, const BatchSolve& init, double* sums, int32_t* cnt, int k,
+                             int d, hipStream_t stream) {
+  const int dm = padded_dim(d);
+  int64_t blocks = (static_cast<int64_t>(k) * dm + 255) / 256;
+  if (blocks > 256) blocks = 256;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(solve_start_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, Cinc,
+                     deginc, cw, degw, sv, init, sums, cnt, k, d, dm);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(BM_EDEVICE, "solve start launch failed: %s", hipGetErrorString(e));
   return BM_OK;
 }
 

@@ -37,6 +37,10 @@ enum Counter {
   kCntTicksEmit = 17,
   kCntTicksAssign = 18,  // Lloyd pass: assignment + local accumulation / global flush
   kCntTicksFlush = 19,
+  kCntTicksSeedInit = 20,    // K-means++: D^2 to the active slots (with its barrier)
+  kCntTicksSeedLocate = 21,  //   per pick: total weight, owner search, candidates (barrier)
+  kCntTicksSeedPot = 22,     //   potentials of the candidates (barrier)
+  kCntTicksSeedUpdate = 23,  //   placement and D^2 update (barrier)
 };
 
 enum SolverError {
@@ -211,6 +215,11 @@ bm_status launch_batch_update(BatchSolve* sv, int n_solves, const double* tile_f
                               int32_t* cnt, float* C, float* Cpad, double* C64, uint8_t* deg, int d,
                               int max_iter, double tol, int stop_rule, int* running,
                               hipStream_t stream, int kmax);
+// One solve's start (sv[0] = init; working centroids and flags copied from
+// the incumbent; sums and counts cleared).
+bm_status launch_solve_start(const float* Cinc, const uint8_t* deginc, float* cw, uint8_t* degw,
+                             BatchSolve* sv, const BatchSolve& init, double* sums, int32_t* cnt, int k,
+                             int d, hipStream_t stream);
 bm_status launch_batch_init(const float* C, double* C64, float* Cpad, int64_t rows, int d,
                             hipStream_t stream);
 bm_status launch_pad_rows(const float* P, float* Pp, int64_t rows, int d, hipStream_t stream);

@@ -38,8 +38,8 @@ struct Lds {
   int* degf;         // degenerate flags
   int* tmpi;         // scan scratch
   double* tmpd;      // reduction scratch
-  int* misc;         // [0] number of active slots, [1] chosen bucket, [2] hit flag
-  int64_t* misc64;   // [0] bucket count, [1] found row, [2] fallback row, [3] pick
+  int* misc;         // [0] number of active slots, [1] chosen bucket, [2] hit flag, [6] last weighted row
+  int64_t* misc64;   // [0] bucket count, [1] found row, [2] fallback row, [3] pick, [4..] draws
   double* miscd;     // [0] broadcast value, [1..] per-trial scratch
   double* c64;       // k x d FP64 means (when they fit)
   unsigned char* B;  // phase-local region
@@ -70,7 +70,7 @@ __host__ __device__ inline LdsPlan plan_lds(int dm, int k, int d, bool sums_in_l
   p.tmpi = o; o = align16(o + sizeof(int) * 32);
   p.tmpd = o; o = align16(o + sizeof(double) * 32);
   p.misc = o; o = align16(o + sizeof(int) * 8);
-  p.misc64 = o; o = align16(o + sizeof(int64_t) * 8);
+  p.misc64 = o; o = align16(o + sizeof(int64_t) * (4 + kMaxTrials));
   p.miscd = o; o = align16(o + sizeof(double) * (4 + 4 * kMaxTrials));
   p.c64 = o; o = align16(o + (c64_in_lds ? sizeof(double) * size_t(k) * d : 0));
   p.B = o;
@@ -707,7 +707,160 @@ __device__ __forceinline__ void dist2_f64_candidates(const float* __restrict__ p
   }
 }
 
+// Smallest FP64 squared distance of the sample row at p to the active slots
+// act[0 .. na-1] of C (LDS, DM wide): the same dimension-order FMA chain as
+// dist2_f64_row for every slot, run for kMinBatch slots at once over 8
+// coordinates at a time, so the row is streamed rather than held and the
+// chains are independent.
+constexpr int kMinBatch = 8;
 template <int DM>
+__device__ __forceinline__ double min_dist2_f64_stream(const float* __restrict__ p, int d,
+                                                       const float* __restrict__ C,
+                                                       const int* __restrict__ act, int na) {
+  double best = __builtin_inf();
+  for (int a0 = 0; a0 < na; a0 += kMinBatch) {
+    double acc[kMinBatch];
+    int off[kMinBatch];
+#pragma unroll
+    for (int u = 0; u < kMinBatch; ++u) {
+      acc[u] = 0.0;
+      off[u] = act[a0 + u < na ? a0 + u : na - 1] * DM;
+    }
+#pragma unroll 1
+    for (int t0 = 0; t0 < DM; t0 += 8) {
+      float xc[8];
+      if ((d & 3) == 0) {
+#pragma unroll
+        for (int u = 0; u < 8; u += 4) {
+          if (t0 + u < d) {
+            const float4 v = *reinterpret_cast<const float4*>(p + t0 + u);
+            xc[u] = v.x;
+            xc[u + 1] = v.y;
+            xc[u + 2] = v.z;
+            xc[u + 3] = v.w;
+          } else {
+            xc[u] = xc[u + 1] = xc[u + 2] = xc[u + 3] = 0.f;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xc[u] = (t0 + u < d) ? p[t0 + u] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < kMinBatch; ++u) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          if (t0 + v < DM) {  // DM is a multiple of 4, not always of 8 (72 is)
+            const double e = static_cast<double>(xc[v]) - static_cast<double>(C[off[u] + t0 + v]);
+            acc[u] = __builtin_fma(e, e, acc[u]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kMinBatch; ++u)
+      if (a0 + u < na && acc[u] < best) best = acc[u];
+  }
+  return best;
+}
+
+// The row of chunk [o0, o1) whose running weight sum (from `base`, rows in
+// index order) first exceeds `target`; every workgroup calls it with the same
+// arguments and gets the same row.  Thread tid holds the weights of its run of
+// rpt consecutive rows (when rpt <= kLocRows, loaded by the caller), one
+// block-wide scan orders the runs, and the thread whose run holds the target
+// walks it.  A target beyond the chunk's total (rounding) takes the chunk's
+// last row with weight.  Returns the row and sets *near when the target lies
+// within 1e-12 W of the row's boundaries.  Longer runs are read from memory.
+constexpr int kLocRows = 4;
+__device__ __forceinline__ void chunk_run(int64_t o0, int64_t o1, int64_t* i0, int* nr) {
+  const int64_t rpt = (o1 - o0 + kBlock - 1) / kBlock;
+  const int64_t a = o0 + threadIdx.x * rpt < o1 ? o0 + threadIdx.x * rpt : o1;
+  const int64_t b = a + rpt < o1 ? a + rpt : o1;
+  *i0 = a;
+  *nr = static_cast<int>(b - a);
+}
+
+__device__ __forceinline__ void load_run(const double* __restrict__ w, int64_t o0, int64_t o1,
+                                         double (&wv)[kLocRows]) {
+  int64_t i0;
+  int nr;
+  chunk_run(o0, o1, &i0, &nr);
+#pragma unroll
+  for (int q = 0; q < kLocRows; ++q) wv[q] = q < nr ? w[i0 + q] : 0.0;
+}
+
+// REG: the run's weights are wv (rpt <= kLocRows); otherwise they are read
+// from w.
+template <bool REG>
+__device__ __forceinline__ int64_t locate_in_chunk(const double (&wv)[kLocRows], const double* __restrict__ w,
+                                                   int64_t o0, int64_t o1, double base, double target,
+                                                   double W, Lds& L, bool* near) {
+  const int tid = threadIdx.x;
+  int64_t i0;
+  int nr;
+  chunk_run(o0, o1, &i0, &nr);
+  auto wt = [&](int q) { return REG ? wv[q < kLocRows ? q : 0] : w[i0 + q]; };
+  const int nq = REG ? kLocRows : nr;
+  double local = 0.0;
+#pragma unroll
+  for (int q = 0; q < nq; ++q)
+    if (q < nr) local += wt(q);
+  double tot = 0.0;
+  const double incl = block_inclusive_scan_f64<kBlock>(local, L.tmpd, tot);
+  double* incl_l = reinterpret_cast<double*>(L.B);  // kBlock doubles
+  incl_l[tid] = incl;
+  if (tid == 0) {
+    L.misc[2] = 0x7fffffff;
+    L.misc[6] = -1;
+  }
+  __syncthreads();
+  const double v0 = base + (tid > 0 ? incl_l[tid - 1] : 0.0);
+  if (nr > 0 && v0 + local > target) atomicMin(&L.misc[2], tid);
+  int last = -1;  // last row with weight, for a target beyond the chunk's sum
+#pragma unroll
+  for (int q = 0; q < nq; ++q)
+    if (q < nr && wt(q) > 0.0) last = q;
+  if (last >= 0) atomicMax(&L.misc[6], static_cast<int>(i0 - o0) + last);
+  __syncthreads();
+  if (tid == L.misc[2]) {
+    double run = v0;
+    int64_t pick = i0 + nr - 1;
+    int nb = 0;
+    bool found = false;
+#pragma unroll
+    for (int q = 0; q < nq; ++q) {
+      if (q < nr && !found) {
+        const double prev = run;
+        run += wt(q);
+        if (run > target) {
+          pick = i0 + q;
+          nb = ((run - target) < 1e-12 * W || (target - prev) < 1e-12 * W) ? 1 : 0;
+          found = true;
+        }
+      }
+    }
+    L.misc64[1] = pick;
+    L.misc64[3] = nb;
+  }
+  __syncthreads();
+  int64_t pick;
+  if (L.misc[2] != 0x7fffffff) {
+    pick = L.misc64[1];
+    *near = L.misc64[3] != 0;
+  } else {
+    pick = L.misc[6] >= 0 ? o0 + L.misc[6] : -1;
+    *near = true;
+  }
+  __syncthreads();
+  return pick;
+}
+
+// LEAN (the reseeding kernel): the D^2 pass streams the rows over batches of
+// slots, and every workgroup locates the draws itself (no barrier); the
+// persistent solver keeps the owning workgroup's search and a barrier, which
+// need fewer registers there.
+template <int DM, bool LEAN>
 __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32_t t, int64_t r0, int64_t r1,
                              bool cached, const RowCache<DM>& rc, int64_t& nd, int64_t& nres) {
   const int tid = threadIdx.x;
@@ -735,23 +888,39 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
     }
   };
   auto get_w = [&](int64_t tile, int64_t i) { return cached ? w_reg : a.w[i]; };
+  // LEAN: the weights also go to a.w in cached mode (every workgroup reads
+  // the chunk that holds a draw's target)
   auto set_w = [&](int64_t i, double v) {
     if (cached) w_reg = v;
-    else a.w[i] = v;
+    if (LEAN || !cached) a.w[i] = v;
   };
 
+  // phase ticks of workgroup 0, kept in registers and added to the counters
+  // once at the end
+  uint64_t tk = wall_clock64();
+  uint64_t ticks[4] = {0, 0, 0, 0};
+  auto tick = [&](int c) {
+    if (!LEAN) return;
+    const uint64_t now = wall_clock64();
+    ticks[c - kCntTicksSeedInit] += now - tk;
+    tk = now;
+  };
   if (L.misc[0] > 0) {
     const int na = L.misc[0];
     double part = 0.0;
     for (int64_t tile = 0; tile < tiles; ++tile) {
       const int64_t i = r0 + tile * kBlock + tid;
       if (i >= r1) continue;
-      float x[DM];
-      row(tile, x);
       double best = __builtin_inf();
-      for (int aa = 0; aa < na; ++aa) {
-        const double dd = dist2_f64_row<DM>(x, L.C + L.act[aa] * DM);
-        if (dd < best) best = dd;
+      if (cached || !LEAN) {
+        float x[DM];
+        row(tile, x);
+        for (int aa = 0; aa < na; ++aa) {
+          const double dd = dist2_f64_row<DM>(x, L.C + L.act[aa] * DM);
+          if (dd < best) best = dd;
+        }
+      } else {
+        best = min_dist2_f64_stream<DM>(a.P + static_cast<size_t>(i) * d, d, L.C, L.act, na);
       }
       set_w(i, best);
       part += best;
@@ -760,6 +929,7 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
     if (tid == 0) a.wsum[g] = ws;
     nd += s * na;
     if (!sync_grid(a)) return false;
+    tick(kCntTicksSeedInit);
   }
 
   for (int j = 0; j < k; ++j) {
@@ -809,66 +979,113 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
       const double W = L.miscd[0];
       if (W == 0.0) break;  // every remaining D^2 is zero: leave the slots degenerate
       q += trials;
-      for (int l = 0; l < trials; ++l) {
-        if (owner[l] != g) continue;
-        const double target = tgt[l];
-        double run = basev[l];
-        if (tid == 0) { L.misc64[1] = -1; L.misc64[3] = 0; }
-        __syncthreads();
-        for (int64_t tile = 0; tile < tiles; ++tile) {
-          const int64_t i = r0 + tile * kBlock + tid;
-          const double wi = (i < r1) ? get_w(tile, i) : 0.0;
-          double tot = 0.0;
-          const double incl = block_inclusive_scan_f64<kBlock>(wi, L.tmpd, tot);
-          const double v = run + incl;
-          const bool hit = (i < r1) && (v > target);
-          // first hitting row of the tile: minimum over hitting threads
-          if (tid == 0) L.misc[2] = 0x7fffffff;
-          __syncthreads();
-          if (hit) atomicMin(&L.misc[2], tid);
-          __syncthreads();
-          const int first = L.misc[2];
-          if (first != 0x7fffffff) {
-            if (tid == first) {
-              L.misc64[1] = i;
-              const double prev = v - wi;
-              L.misc64[3] = ((v - target) < 1e-12 * W || (target - prev) < 1e-12 * W) ? 1 : 0;
-            }
-            __syncthreads();
-            break;
+      int64_t cands[kMaxTrials];
+      bool valid = true;
+      if constexpr (LEAN) {
+        // every workgroup locates each draw in the chunk that holds it (the
+        // weights of the last update are visible since its barrier); the next
+        // draw's weights load while one is located
+        const int64_t rpw = (s + G - 1) / G;
+        const bool reg = (rpw + kBlock - 1) / kBlock <= kLocRows;
+        auto chunk_of = [&](int l, int64_t* o0, int64_t* o1) {
+          *o0 = imin64(s, static_cast<int64_t>(owner[l]) * rpw);
+          *o1 = imin64(s, *o0 + rpw);
+        };
+        double wv[kLocRows], wn[kLocRows];
+        {
+          int64_t o0, o1;
+          chunk_of(0, &o0, &o1);
+          if (reg) load_run(a.w, o0, o1, wv);
+        }
+        int64_t* cand_l = L.misc64 + 4;  // per-draw candidate rows
+#pragma unroll 1
+        for (int l = 0; l < trials; ++l) {
+          int64_t o0, o1;
+          if (reg && l + 1 < trials) {
+            chunk_of(l + 1, &o0, &o1);
+            load_run(a.w, o0, o1, wn);
           }
-          run += tot;
+          chunk_of(l, &o0, &o1);
+          bool near = false;
+          const int64_t c = reg ? locate_in_chunk<true>(wv, a.w, o0, o1, basev[l], tgt[l], W, L, &near)
+                                : locate_in_chunk<false>(wv, a.w, o0, o1, basev[l], tgt[l], W, L, &near);
+          if (tid == 0) cand_l[l] = c;
+          if (near && g == 0 && tid == 0)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntBoundary]), 1ull);
+#pragma unroll
+          for (int q = 0; q < kLocRows; ++q) wv[q] = wn[q];
         }
         __syncthreads();
-        if (L.misc64[1] < 0) {
-          // rounding left the target beyond this chunk: last row with weight
-          if (tid == 0) L.misc[2] = -1;
+#pragma unroll
+        for (int l = 0; l < kMaxTrials; ++l) {
+          cands[l] = l < trials ? cand_l[l] : 0;
+          valid = valid && (l >= trials || (cands[l] >= 0 && cands[l] < s));
+        }
+        tick(kCntTicksSeedLocate);
+        if (!valid) {
+          if (tid == 0) set_err(a, kErrSeed);
+          return false;
+        }
+      } else {
+        for (int l = 0; l < trials; ++l) {
+          if (owner[l] != g) continue;
+          const double target = tgt[l];
+          double run = basev[l];
+          if (tid == 0) { L.misc64[1] = -1; L.misc64[3] = 0; }
           __syncthreads();
           for (int64_t tile = 0; tile < tiles; ++tile) {
             const int64_t i = r0 + tile * kBlock + tid;
-            if (i < r1 && get_w(tile, i) > 0.0) atomicMax(&L.misc[2], static_cast<int>(i - r0));
+            const double wi = (i < r1) ? get_w(tile, i) : 0.0;
+            double tot = 0.0;
+            const double incl = block_inclusive_scan_f64<kBlock>(wi, L.tmpd, tot);
+            const double v = run + incl;
+            const bool hit = (i < r1) && (v > target);
+            // first hitting row of the tile: minimum over hitting threads
+            if (tid == 0) L.misc[2] = 0x7fffffff;
+            __syncthreads();
+            if (hit) atomicMin(&L.misc[2], tid);
+            __syncthreads();
+            const int first = L.misc[2];
+            if (first != 0x7fffffff) {
+              if (tid == first) {
+                L.misc64[1] = i;
+                const double prev = v - wi;
+                L.misc64[3] = ((v - target) < 1e-12 * W || (target - prev) < 1e-12 * W) ? 1 : 0;
+              }
+              __syncthreads();
+              break;
+            }
+            run += tot;
           }
           __syncthreads();
+          if (L.misc64[1] < 0) {
+            // rounding left the target beyond this chunk: last row with weight
+            if (tid == 0) L.misc[2] = -1;
+            __syncthreads();
+            for (int64_t tile = 0; tile < tiles; ++tile) {
+              const int64_t i = r0 + tile * kBlock + tid;
+              if (i < r1 && get_w(tile, i) > 0.0) atomicMax(&L.misc[2], static_cast<int>(i - r0));
+            }
+            __syncthreads();
+            if (tid == 0) {
+              L.misc64[1] = (L.misc[2] >= 0) ? r0 + L.misc[2] : -1;
+              L.misc64[3] = 1;
+            }
+            __syncthreads();
+          }
           if (tid == 0) {
-            L.misc64[1] = (L.misc[2] >= 0) ? r0 + L.misc[2] : -1;
-            L.misc64[3] = 1;
+            a.cand[l] = L.misc64[1];
+            if (L.misc64[3]) atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntBoundary]), 1ull);
+            if (L.misc64[1] < 0) set_err(a, kErrSeed);
           }
           __syncthreads();
         }
-        if (tid == 0) {
-          a.cand[l] = L.misc64[1];
-          if (L.misc64[3]) atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntBoundary]), 1ull);
-          if (L.misc64[1] < 0) set_err(a, kErrSeed);
-        }
-        __syncthreads();
-      }
-      if (!sync_grid(a)) return false;
-      int64_t cands[kMaxTrials];
-      bool valid = true;
+        if (!sync_grid(a)) return false;
 #pragma unroll
-      for (int l = 0; l < kMaxTrials; ++l) {
-        cands[l] = (l < trials) ? a.cand[l] : 0;
-        valid = valid && cands[l] >= 0 && cands[l] < s;
+        for (int l = 0; l < kMaxTrials; ++l) {
+          cands[l] = (l < trials) ? a.cand[l] : 0;
+          valid = valid && cands[l] >= 0 && cands[l] < s;
+        }
       }
       if (!valid) {
         if (tid == 0) set_err(a, kErrSeed);
@@ -923,6 +1140,7 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
         }
         nd += s * trials;
         if (!sync_grid(a)) return false;
+        tick(kCntTicksSeedPot);
         int best = 0;
         double best_phi = __builtin_inf();
         for (int l = 0; l < trials; ++l) {
@@ -974,7 +1192,10 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
     nres += 1;
     rebuild_active(L, k);
     if (!sync_grid(a)) return false;
+    tick(kCntTicksSeedUpdate);
   }
+  if (LEAN && g == 0 && tid == 0)
+    for (int c = 0; c < 4; ++c) a.counters[kCntTicksSeedInit + c] += static_cast<int64_t>(ticks[c]);
   return true;
 }
 
@@ -1419,7 +1640,7 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
       if (a.init_forgy) {
         forgy_phase<DM>(a, L, t, c_reseeded);
       } else {
-        ok = reseed_phase<DM>(a, L, t, r0, r1, cached, rc, c_nd, c_reseeded);
+        ok = reseed_phase<DM, false>(a, L, t, r0, r1, cached, rc, c_nd, c_reseeded);
         if (!ok) break;
       }
     }
@@ -1458,6 +1679,47 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
     a.counters[kCntTicksLloyd] = static_cast<int64_t>(c_tlloyd);
     a.counters[kCntTicksPass] = static_cast<int64_t>(c_tpass);
     a.counters[kCntTicksPost] = static_cast<int64_t>(c_tpost);
+  }
+}
+
+// The reseeding step alone (one sample already in a.P, no Lloyd, no
+// keep-the-best): the solver's K-means++ (or Forgy) phase on the incumbent,
+// whose result replaces the incumbent.  A kernel of its own, so its registers
+// are not sized by the other phases.
+template <int DM>
+__global__ void __launch_bounds__(kBlock) seed_kernel(SolverArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds != 0, a.c64_in_lds != 0);
+  Lds L = carve(lds_raw, pl);
+  const int tid = threadIdx.x;
+  const int g = blockIdx.x;
+  const int G = gridDim.x;
+  const int64_t rpw = (a.s + G - 1) / G;
+  const int64_t r0 = imin64(a.s, static_cast<int64_t>(g) * rpw);
+  const int64_t r1 = imin64(a.s, r0 + rpw);
+  const uint32_t t = static_cast<uint32_t>(a.t0);
+  int64_t c_reseeded = 0, c_nd = 0;
+  const uint64_t clk0 = wall_clock64();
+  load_incumbent<DM>(a, L);
+  RowCache<DM> rc;
+  const bool cached = RowCache<DM>::kRows > 0 && (r1 - r0) <= kBlock;
+  if (cached) {
+    const int64_t i = r0 + tid;
+    if (i < r1) load_row_f32<DM>(a.P + static_cast<size_t>(i) * a.d, a.d, rc.x[0]);
+  }
+  bool ok = true;
+  if (L.misc[0] < a.k) {
+    if (a.init_forgy) forgy_phase<DM>(a, L, t, c_reseeded);
+    else ok = reseed_phase<DM, true>(a, L, t, r0, r1, cached, rc, c_nd, c_reseeded);
+  }
+  if (!ok) return;
+  if (g == 0) store_incumbent<DM>(a, L, 0.0);
+  if (g == 0 && tid == 0) {
+    a.counters[kCntReseeded] = c_reseeded;
+    a.counters[kCntND] = c_nd;
+    a.counters[kCntSamples] = 1;
+    a.counters[kCntTicksSeed] = static_cast<int64_t>(wall_clock64() - clk0);
+    if (a.sample_f) a.sample_f[0] = 0.0;
   }
 }
 
@@ -1566,6 +1828,20 @@ size_t solver_lds_bytes(int dm, int k, int d, bool sums_in_lds, bool c64_in_lds)
   return plan_lds(dm, k, d, sums_in_lds, c64_in_lds).total;
 }
 
+static const void* seed_fn(int dm) {
+  switch (dm) {
+    case 4: return reinterpret_cast<const void*>(&seed_kernel<4>);
+    case 8: return reinterpret_cast<const void*>(&seed_kernel<8>);
+    case 16: return reinterpret_cast<const void*>(&seed_kernel<16>);
+    case 32: return reinterpret_cast<const void*>(&seed_kernel<32>);
+    case 64: return reinterpret_cast<const void*>(&seed_kernel<64>);
+    case 72: return reinterpret_cast<const void*>(&seed_kernel<72>);
+    case 128: return reinterpret_cast<const void*>(&seed_kernel<128>);
+    case 256: return reinterpret_cast<const void*>(&seed_kernel<256>);
+    default: return nullptr;
+  }
+}
+
 static const void* solver_fn(int dm) {
   switch (dm) {
     case 4: return reinterpret_cast<const void*>(&solver_kernel<4>);
@@ -1619,7 +1895,10 @@ bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t s
       !a.err || !a.sample_f || (a.budget_ticks && !a.stop_flag) || grid < 1 || grid > kMaxGrid)
     return set_error(BM_EINVAL, "solver launch with a missing buffer or bad grid %d", grid);
   const int dm = padded_dim(a.d);
-  const void* fn = solver_fn(dm);
+  // the reseeding step alone runs on its own kernel
+  const bool seed_only = a.do_seed && !a.do_lloyd && !a.do_keep && !a.do_sample && !a.do_gather &&
+                         a.T == 1 && !a.init_incumbent && !a.budget_ticks;
+  const void* fn = seed_only ? seed_fn(dm) : solver_fn(dm);
   if (!fn) return set_error(BM_ENOTSUP, "dimension %d exceeds the solver's limit of 256", a.d);
   if (lds > 65536) {
     const hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
