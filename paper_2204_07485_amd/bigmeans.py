@@ -564,16 +564,17 @@ def debug_counters():
     """Raw device counters of this thread's last bigmeans_fit (bm_debug_counters):
     a dict of the per-phase clock ticks and event counts."""
     L = load()
-    out = (ct.c_int64 * 24)()
+    out = (ct.c_int64 * 28)()
     L.bm_debug_counters.argtypes = [ct.c_void_p, ct.c_int32]
     L.bm_debug_counters.restype = ct.c_int32
-    _check(L.bm_debug_counters(out, 24))
+    _check(L.bm_debug_counters(out, 28))
     names = {0: "passes", 1: "reseeded", 2: "replaced", 3: "n_d", 4: "boundary", 5: "samples",
              6: "select_passes", 8: "ticks_sample", 9: "ticks_seed", 10: "ticks_lloyd",
              11: "ticks_pass", 12: "ticks_post", 13: "ticks_barrier", 14: "ticks_collect",
              15: "ticks_collect_wait", 16: "ticks_select", 17: "ticks_emit", 18: "ticks_assign",
              19: "ticks_flush", 20: "ticks_seed_init", 21: "ticks_seed_locate",
-             22: "ticks_seed_pot", 23: "ticks_seed_update"}
+             22: "ticks_seed_pot", 23: "ticks_seed_update", 24: "ticks_assign_init",
+             25: "ticks_assign_rows", 26: "ticks_assign_sum"}
     return {v: int(out[k]) for k, v in names.items()}
 
 

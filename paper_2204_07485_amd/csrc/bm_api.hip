@@ -1104,7 +1104,7 @@ bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int
   const bool polish = o.final_mode == BM_FINAL_POLISH && (sse || labels);
   const bool final_pass = (sse || labels) && !polish;
   const bool final_mfma = final_pass && o.precision == BM_PREC_BF16_MFMA;
-  int final_grid = final_pass ? assign_grid(n) : 0;
+  int final_grid = final_pass ? assign_grid(n, d) : 0;
   if (final_mfma && (st = plan_assign_mfma(X, n, d, k, &final_grid)) != BM_OK) return st;
   // with a time budget the samples are drawn a few at a time (most of a
   // larger batch could go unused)
@@ -1294,7 +1294,7 @@ bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, con
   hipStream_t stream = static_cast<hipStream_t>(o.stream);
   const bool mfma = o.precision == BM_PREC_BF16_MFMA;
   std::lock_guard<std::mutex> lock(g_mu);
-  int grid = assign_grid(n);
+  int grid = assign_grid(n, d);
   if (mfma && (st = plan_assign_mfma(X, n, d, k, &grid)) != BM_OK) return st;
   uint8_t* deg_p = nullptr;
   double* partial_p = nullptr;
@@ -1555,7 +1555,7 @@ static bm_status collective_run(const void* X, int64_t n, int32_t d, int32_t k, 
     return set_error(BM_ENOTSUP, "the %d samples of a round do not fit the sample buffers", W);
   const bool final_pass = sse || labels;
   const bool final_mfma = final_pass && o.precision == BM_PREC_BF16_MFMA;
-  int final_grid = final_pass ? assign_grid(n) : 0;
+  int final_grid = final_pass ? assign_grid(n, d) : 0;
   if (final_mfma && (st = plan_assign_mfma(X, n, d, k, &final_grid)) != BM_OK) return st;
   SolverBuffers b;
   memset(&b.a, 0, sizeof b.a);

@@ -3,9 +3,11 @@
 // non-degenerate centroid, and the objective of Eq. (1) is summed in FP64.
 //
 // A grid of a few workgroups per CU streams X once from HBM (each thread owns
-// whole rows, held in registers); the centroids sit in LDS, padded with zeros
-// to a multiple of 4 columns so the inner loop reads them as broadcast
-// 16-byte LDS loads.  The nearest centroid is chosen with FP32 direct
+// whole rows, held in registers, and for rows up to 64 wide loads its next row
+// while it processes one); the centroids sit in LDS, padded with zeros to a
+// multiple of 4 columns so the inner loop reads them as broadcast 16-byte LDS
+// loads (four centroid chains at a time), or, for unpadded rows up to 32 wide,
+// come through the scalar cache as SGPR operands.  The nearest centroid is chosen with FP32 direct
 // differences (FMA chain in dimension order; exact ties to the lowest index);
 // the chosen distance is then recomputed in FP64 for the objective.  Each workgroup
 // writes its FP64 partial objective; the last workgroup to finish adds the
@@ -52,20 +54,44 @@ __global__ void __launch_bounds__(kAssignBlock)
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kAssignBlock;
   // with no active centroid (a failed fit) the outputs are left untouched
   const int64_t n_rows = na > 0 ? n : 0;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kAssignBlock + tid; i < n_rows; i += stride) {
-    float x[DM];
+  // the next row's loads are in flight while a row is processed (rows up to
+  // 64 wide; wider ones would double too many registers)
+  constexpr bool kAhead = DM <= 64;
+  auto load = [&](int64_t i, float (&x)[DM]) {
     if (BF16) {
       load_row_bf16<DM>(static_cast<const uint16_t*>(Xv) + static_cast<size_t>(i) * d, d, x);
     } else {
       load_row_f32<DM>(static_cast<const float*>(Xv) + static_cast<size_t>(i) * d, d, x);
     }
+  };
+  int64_t i = static_cast<int64_t>(blockIdx.x) * kAssignBlock + tid;
+  float x[DM];
+  if (kAhead && i < n_rows) load(i, x);
+  for (; i < n_rows; i += stride) {
+    float xn[kAhead ? DM : 1];
+    const bool more = kAhead && i + stride < n_rows;
+    if constexpr (kAhead) {
+      if (more) load(i + stride, xn);
+    } else {
+      load(i, x);
+    }
     int bj;
     float bd;
-    nearest_f32<DM>(x, Cl, act, na, bj, bd);
+    // unpadded rows (d == DM): the centroid values come through the scalar
+    // cache as SGPR operands, sparing the LDS bandwidth of 64 broadcast lanes
+    if (DM <= 32 && d == DM) nearest_f32_sgpr<DM>(x, C, act, na, bj, bd);
+    else if (DM <= 32) nearest_f32_x4<DM>(x, Cl, act, na, bj, bd);
+    else nearest_f32<DM>(x, Cl, act, na, bj, bd);
     const double exact = dist2_f64_row<DM>(x, Cl + bj * DM);
     if (labels) labels[i] = bj;
     if (min_d2) min_d2[i] = static_cast<float>(exact);
     sse += exact;
+    if constexpr (kAhead) {
+      if (more) {
+#pragma unroll
+        for (int t = 0; t < DM; ++t) x[t] = xn[t];
+      }
+    }
   }
   const double bsum = block_sum_f64<kAssignBlock>(sse, s_tmp);
   if (tid == 0) {
@@ -110,12 +136,15 @@ const void* pick_assign(int dm, bool bf16) {
 
 }  // namespace
 
-int assign_grid(int64_t n) {
+int assign_grid(int64_t n, int d) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  // rows up to 64 wide: four workgroups per CU, each thread takes several
+  // rows and the next row's loads overlap the current row's distances;
+  // wider rows: eight
   const int64_t want = (n + kAssignBlock - 1) / kAssignBlock;
-  const int64_t cap = static_cast<int64_t>(cus) * 8;
+  const int64_t cap = static_cast<int64_t>(cus) * (padded_dim(d) <= 64 ? 4 : 8);
   int64_t g = want < cap ? want : cap;
   return static_cast<int>(g < 1 ? 1 : g);
 }

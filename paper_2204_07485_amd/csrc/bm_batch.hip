@@ -150,18 +150,29 @@ __global__ void __launch_bounds__(kBatchBlock)
     const int64_t rend = s_row0 + s_s;
     const int64_t r1 = r0 + tile_rows < rend ? r0 + tile_rows : rend;
     double f = 0.0;
-    for (int64_t i = r0 + tid; i < r1; i += kBatchBlock) {
-      float x[DM];
-      {  // rows are DM wide and zero padded: 16-byte loads, no column guard
-        const float4* r4 = reinterpret_cast<const float4*>(Pp + static_cast<size_t>(i) * DM);
+    // rows are DM wide and zero padded: 16-byte loads, no column guard; up to
+    // 32 columns the next row's loads are in flight while a row is processed
+    constexpr bool kAhead = DM <= 32;
+    auto load = [&](int64_t i, float (&x)[DM]) {
+      const float4* r4 = reinterpret_cast<const float4*>(Pp + static_cast<size_t>(i) * DM);
 #pragma unroll
-        for (int q = 0; q < DM / 4; ++q) {
-          const float4 v = r4[q];
-          x[4 * q + 0] = v.x;
-          x[4 * q + 1] = v.y;
-          x[4 * q + 2] = v.z;
-          x[4 * q + 3] = v.w;
-        }
+      for (int q = 0; q < DM / 4; ++q) {
+        const float4 v = r4[q];
+        x[4 * q + 0] = v.x;
+        x[4 * q + 1] = v.y;
+        x[4 * q + 2] = v.z;
+        x[4 * q + 3] = v.w;
+      }
+    };
+    float x[DM];
+    if (kAhead && r0 + tid < r1) load(r0 + tid, x);
+    for (int64_t i = r0 + tid; i < r1; i += kBatchBlock) {
+      float xn[kAhead ? DM : 1];
+      const bool more = kAhead && i + kBatchBlock < r1;
+      if constexpr (kAhead) {
+        if (more) load(i + kBatchBlock, xn);
+      } else {
+        load(i, x);
       }
       int bj;
       float bd;
@@ -172,7 +183,7 @@ __global__ void __launch_bounds__(kBatchBlock)
       } else {
         nearest_f32_sgpr<DM>(x, Cpad + static_cast<size_t>(c0) * DM, act, na, bj, bd);
       }
-      if (bj < 0) continue;  // no active centroid: nothing to assign or add
+      if (bj >= 0) {  // else no active centroid: nothing to assign or add
       if (labels && !dry) labels[i] = bj;
       const float* cw = Cl + bj * DM;
       if (accumulate) {
@@ -191,6 +202,13 @@ __global__ void __launch_bounds__(kBatchBlock)
         f += acc;
       } else {
         f += dist2_f64_row<DM>(x, cw);
+      }
+      }
+      if constexpr (kAhead) {
+        if (more) {
+#pragma unroll
+          for (int t2 = 0; t2 < DM; ++t2) x[t2] = xn[t2];
+        }
       }
     }
     const double ft = block_sum_f64<kBatchBlock>(f, s_tmp);

@@ -270,6 +270,42 @@ __device__ __forceinline__ float dist2_f32(const float (&x)[DM], const float* __
   return acc;
 }
 
+// dist2_f32 for four centroid rows at once: four independent FMA chains,
+// each with exactly dist2_f32's arithmetic and order, interleaved so that
+// their latencies overlap.
+template <int DM>
+__device__ __forceinline__ void dist2_f32_x4(const float (&x)[DM], const float* __restrict__ c0,
+                                             const float* __restrict__ c1, const float* __restrict__ c2,
+                                             const float* __restrict__ c3, float (&out)[4]) {
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+  for (int t = 0; t < DM; t += 4) {
+    const float4 v0 = *reinterpret_cast<const float4*>(c0 + t);
+    const float4 v1 = *reinterpret_cast<const float4*>(c1 + t);
+    const float4 v2 = *reinterpret_cast<const float4*>(c2 + t);
+    const float4 v3 = *reinterpret_cast<const float4*>(c3 + t);
+    const float w0[4] = {v0.x, v0.y, v0.z, v0.w};
+    const float w1[4] = {v1.x, v1.y, v1.z, v1.w};
+    const float w2[4] = {v2.x, v2.y, v2.z, v2.w};
+    const float w3[4] = {v3.x, v3.y, v3.z, v3.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float e0 = x[t + q] - w0[q];
+      const float e1 = x[t + q] - w1[q];
+      const float e2 = x[t + q] - w2[q];
+      const float e3 = x[t + q] - w3[q];
+      a0 = __builtin_fmaf(e0, e0, a0);
+      a1 = __builtin_fmaf(e1, e1, a1);
+      a2 = __builtin_fmaf(e2, e2, a2);
+      a3 = __builtin_fmaf(e3, e3, a3);
+    }
+  }
+  out[0] = a0;
+  out[1] = a1;
+  out[2] = a2;
+  out[3] = a3;
+}
+
 // Nearest active centroid: `act` lists the na active slots in ascending order,
 // so a strict comparison keeps the lowest index on exact ties.
 template <int DM>
@@ -280,6 +316,38 @@ __device__ __forceinline__ void nearest_f32(const float (&x)[DM], const float* _
   best_j = na > 0 ? act[0] : -1;
   best_d = __builtin_inff();
   for (int a = 0; a < na; ++a) {
+    const int j = act[a];
+    const float v = dist2_f32<DM>(x, Cl + j * DM);
+    if (v < best_d) {
+      best_d = v;
+      best_j = j;
+    }
+  }
+}
+
+// nearest_f32 with four active slots' chains at a time (dist2_f32_x4),
+// compared in ascending slot order: the same distances and the same winner.
+template <int DM>
+__device__ __forceinline__ void nearest_f32_x4(const float (&x)[DM], const float* __restrict__ Cl,
+                                               const int* __restrict__ act, int na, int& best_j,
+                                               float& best_d) {
+  best_j = na > 0 ? act[0] : -1;
+  best_d = __builtin_inff();
+  int a = 0;
+  for (; a + 4 <= na; a += 4) {
+    const int j0 = act[a], j1 = act[a + 1], j2 = act[a + 2], j3 = act[a + 3];
+    float v[4];
+    dist2_f32_x4<DM>(x, Cl + j0 * DM, Cl + j1 * DM, Cl + j2 * DM, Cl + j3 * DM, v);
+    const int jj[4] = {j0, j1, j2, j3};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (v[u] < best_d) {
+        best_d = v[u];
+        best_j = jj[u];
+      }
+    }
+  }
+  for (; a < na; ++a) {
     const int j = act[a];
     const float v = dist2_f32<DM>(x, Cl + j * DM);
     if (v < best_d) {

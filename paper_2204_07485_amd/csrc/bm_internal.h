@@ -14,7 +14,7 @@ constexpr int kMaxTrials = 8;       // K-means++ candidates per centre
 constexpr int kReplicas = 1;        // copies of the cluster-sum accumulators (workgroup g
                                     // adds into copy g % kReplicas); one measured best
 constexpr int kMaxGrid = 1024;      // solver workgroups
-constexpr int kNumCounters = 24;
+constexpr int kNumCounters = 28;
 constexpr unsigned int kDefaultSpinLimit = 1u << 24;
 
 enum Counter {
@@ -41,6 +41,9 @@ enum Counter {
   kCntTicksSeedLocate = 21,  //   per pick: total weight, owner search, candidates (barrier)
   kCntTicksSeedPot = 22,     //   potentials of the candidates (barrier)
   kCntTicksSeedUpdate = 23,  //   placement and D^2 update (barrier)
+  kCntTicksAssignInit = 24,  // Lloyd pass: clearing the ring slot and the LDS sums
+  kCntTicksAssignRows = 25,  //   the rows: nearest slot, objective term, LDS accumulation
+  kCntTicksAssignSum = 26,   //   the workgroup's objective sum
 };
 
 enum SolverError {
@@ -172,7 +175,7 @@ bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float
                         const uint8_t* deg_dev, int k, int32_t* labels, float* min_d2,
                         double* partial, unsigned int* done, double* sse_dev, int grid,
                         hipStream_t stream);
-int assign_grid(int64_t n);
+int assign_grid(int64_t n, int d);
 
 // Batched Lloyd (bm_batch.hip): per-solve state, laid out in device memory.
 constexpr int kSolveRunning = 0;  // next round: assignment + update

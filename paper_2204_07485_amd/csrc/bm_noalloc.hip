@@ -80,7 +80,7 @@ extern "C" bm_status kmeans_assign_noalloc(const void* X, int64_t n, int32_t d, 
   unsigned char* base = nullptr;
   if ((st = scratch_address(dev, &base)) != BM_OK) return st;
 
-  int grid = assign_grid(n);
+  int grid = assign_grid(n, d);
   if (mfma && (st = plan_assign_mfma(X, n, d, k, &grid)) != BM_OK) return st;
   // layout: flags | partials | counter | objective | recheck count
   const size_t off_deg = 0;

@@ -1215,7 +1215,21 @@ __device__ __forceinline__ void assign_row(const SolverArgs& a, Lds& L, const fl
   // smaller, and the strict comparison keeps the lowest index on exact ties
   bj = L.act[0];
   bd = __builtin_inff();
-  for (int j = 0; j < a.k; ++j) {
+  int j = 0;
+  if (DM <= 32) {  // four slots at a time (their chains overlap), compared in index order
+    for (; j + 4 <= a.k; j += 4) {
+      float v[4];
+      dist2_f32_x4<DM>(x, L.C + j * DM, L.C + (j + 1) * DM, L.C + (j + 2) * DM, L.C + (j + 3) * DM, v);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (v[u] < bd) {
+          bd = v[u];
+          bj = j + u;
+        }
+      }
+    }
+  }
+  for (; j < a.k; ++j) {
     const float v = dist2_f32<DM>(x, L.C + j * DM);
     if (v < bd) {
       bd = v;
@@ -1267,6 +1281,7 @@ __device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& 
     for (int j = tid; j < k; j += kBlock) cnt_l[j] = 0;
     __syncthreads();
   }
+  const uint64_t a1 = wall_clock64();
   double sse = 0.0;
   auto rows = [&](auto sums_lds_tag, double* sums_dst) {
     constexpr bool kL = decltype(sums_lds_tag)::value;
@@ -1286,6 +1301,8 @@ __device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& 
   };
   if (a.sums_in_lds) rows(std::true_type{}, sums_l);
   else rows(std::false_type{}, ring);
+  __syncthreads();
+  const uint64_t a2 = wall_clock64();
   const double wsse = block_sum_f64<kBlock>(sse, L.tmpd);
   const uint64_t f0 = wall_clock64();
   if (accumulate) {
@@ -1303,6 +1320,9 @@ __device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& 
   const bool ok = sync_grid(a);
   if (g == 0 && tid == 0) {
     a.counters[kCntTicksAssign] += static_cast<int64_t>(f0 - a0);
+    a.counters[kCntTicksAssignInit] += static_cast<int64_t>(a1 - a0);
+    a.counters[kCntTicksAssignRows] += static_cast<int64_t>(a2 - a1);
+    a.counters[kCntTicksAssignSum] += static_cast<int64_t>(f0 - a2);
     a.counters[kCntTicksFlush] += static_cast<int64_t>(b0 - f0);
     a.counters[kCntTicksBarrier] += static_cast<int64_t>(wall_clock64() - b0);
   }
