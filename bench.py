@@ -25,6 +25,7 @@ HBM_PEAK_GBS = 8000.0
 # FP32 direct differences take two VALU instructions (subtract, FMA) per
 # coordinate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 FLOP / 2 instructions
 FP32_DD_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 2 / 1e12
+FP32_MFMA_PEAK_TFLOPS = 157.3  # dense FP32 matrix (MI355X)
 COUNTERS = os.path.join(ROOT, "profiles", "solver_medium_hbm_counters.md")
 
 
@@ -253,10 +254,18 @@ def final_passes(Xmed, gold, reps=5):
             warm.append(bigmeans.last_assign_ms())
         ms = statistics.median(vals)
         algo = n * d * 4 + n * 4
-        res[name] = {"kernel": f"assign_kernel<{ {16: 16, 68: 72}[d] },f32>", "ms_cold": ms,
+        # k d >= 1024 (and d, k >= 8) runs on the matrix cores (same labels)
+        mfma = d >= 8 and k >= 8 and k * d >= 1024
+        kernel = (f"assign_mfma32_kernel<{ {68: 5, 128: 8}[d] },true>" if mfma
+                  else f"assign_kernel<{ {16: 16, 68: 72}[d] },f32>")
+        res[name] = {"kernel": kernel, "ms_cold": ms,
                      "ms_warm": statistics.median(warm), "algorithmic_bytes": algo,
                      "gbs_cold": algo / (ms * 1e-3) / 1e9, "hbm_frac_cold": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "tflops_cold": 2 * n * k * d / (ms * 1e-3) / 1e12}
+        if mfma:  # issued matrix work: k padded to 16-row tiles, d to 16-column chunks
+            kp, dp = 16 * -(-k // 16), 16 * { 68: 5, 128: 8}[d]
+            res[name]["mfma_tflops_cold"] = 2 * n * kp * dp / (ms * 1e-3) / 1e12
+            res[name]["mfma_frac_cold"] = res[name]["mfma_tflops_cold"] / FP32_MFMA_PEAK_TFLOPS
     del Xw, flush
     torch.cuda.empty_cache()
     return res

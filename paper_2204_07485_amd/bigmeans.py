@@ -578,6 +578,16 @@ def debug_counters():
     return {v: int(out[k]) for k, v in names.items()}
 
 
+def debug_fp32_mfma(on):
+    """FP32 full-data assignment: 1 = on the matrix cores when d >= 8,
+    k >= 8 and k d >= 1024 (default), 0 = on the VALU kernel; returns the
+    previous value."""
+    L = load()
+    L.bm_debug_fp32_mfma.argtypes = [ct.c_int32]
+    L.bm_debug_fp32_mfma.restype = ct.c_int32
+    return L.bm_debug_fp32_mfma(on)
+
+
 def debug_mfma_lloyd(on):
     """BF16 matrix-core fits: 1 = sample-level K-means on the matrix cores
     (default), 0 = on the FP32 persistent solver; returns the previous value."""

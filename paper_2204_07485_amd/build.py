@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbigmeans.so")
-SOURCES = ["bm_api.hip", "bm_solver.hip", "bm_assign.hip", "bm_assign_mfma.hip", "bm_batch.hip", "bm_serve.hip",
+SOURCES = ["bm_api.hip", "bm_solver.hip", "bm_assign.hip", "bm_assign_mfma.hip", "bm_assign_mfma32.hip",
+           "bm_batch.hip", "bm_serve.hip",
            "bm_noalloc.hip"]
 ARCH = os.environ.get("BM_OFFLOAD_ARCH", "gfx950")
 

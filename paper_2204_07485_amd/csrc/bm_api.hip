@@ -25,6 +25,8 @@ static std::atomic<int> g_presample_mode{0};
 // BF16 matrix-core fits: 1 = the sample-level K-means on the matrix cores
 // (default), 0 = the FP32 persistent solver for it (a test hook).
 static std::atomic<int> g_mfma_lloyd{1};
+static std::atomic<int> g_fp32_mfma{1};
+bool fp32_mfma_enabled() { return g_fp32_mfma.load() != 0; }
 static thread_local int64_t g_last_rechecked = 0;
 static thread_local double g_last_assign_ms = 0.0;
 static thread_local int32_t g_last_batch_rounds = 0;
@@ -633,12 +635,21 @@ int32_t bm_debug_presample(int32_t mode) {
   return g_presample_mode.exchange(mode);
 }
 
-// Raw per-phase counters of the last bigmeans_fit on this thread.
+// Test hook: BF16 fits' sample-level K-means on the matrix cores (1) or on
+// the FP32 persistent solver (0); returns the previous setting.
 int32_t bm_debug_mfma_lloyd(int32_t on) {
   if (on < 0 || on > 1) return -1;
   return g_mfma_lloyd.exchange(on);
 }
 
+// Test hook: FP32 full-data assignment on the matrix cores (1) or on the VALU
+// kernel (0); returns the previous setting.
+int32_t bm_debug_fp32_mfma(int32_t on) {
+  if (on != 0 && on != 1) return -1;
+  return g_fp32_mfma.exchange(on);
+}
+
+// Raw per-phase counters of the last bigmeans_fit on this thread.
 int32_t bm_debug_counters(int64_t* out, int32_t n) {
   if (!out || n < 1) return BM_EINVAL;
   for (int i = 0; i < n && i < kNumCounters; ++i) out[i] = g_last_counters[i];

@@ -153,6 +153,18 @@ bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float
                         const uint8_t* deg_dev, int k, int32_t* labels, float* min_d2,
                         double* partial, unsigned int* done, double* sse_dev, int grid,
                         hipStream_t stream) {
+  // FP32 rows at least 8 wide against at least 8 centroids with k d >= 1024
+  // (below that the VALU scan is as fast): the matrix-core form (the same
+  // labels, see bm_assign_mfma32.hip), on at most `grid` workgroups (the
+  // caller's partial buffer)
+  if (!x_bf16 && d >= 8 && k >= 8 && k * d >= 1024 && fp32_mfma_enabled()) {
+    int mgrid = 0;
+    if (plan_assign_mfma32(X, n, d, k, &mgrid) == BM_OK) {
+      return launch_assign_mfma32(static_cast<const float*>(X), n, d, C, deg_dev, k, labels, min_d2,
+                                  partial, done, sse_dev, nullptr, mgrid < grid ? mgrid : grid, stream);
+    }
+    clear_error();  // too large for its LDS plan: the VALU form below
+  }
   const int dm = padded_dim(d);
   const void* fn = pick_assign(dm, x_bf16 != 0);
   if (!fn) return set_error(BM_ENOTSUP, "dimension %d exceeds the assign kernel's limit of 256", d);

@@ -233,6 +233,14 @@ bm_status launch_gather_rows(const void* X, int x_bf16, int64_t n, int d, const 
 // picks the grid; the launch writes the same outputs as launch_assign and
 // adds the number of points it recomputed on the FP32 path to *rechecked.
 bm_status plan_assign_mfma(const void* X, int64_t n, int d, int k, int* grid);
+// FP32 X on the matrix cores (bm_assign_mfma32.hip): labels of the FP32
+// direct-difference path; launch_assign takes this form when it applies.
+bm_status plan_assign_mfma32(const void* X, int64_t n, int d, int k, int* grid);
+bm_status launch_assign_mfma32(const float* X, int64_t n, int d, const float* C, const uint8_t* deg_dev,
+                               int k, int32_t* labels, float* min_d2, double* partial,
+                               unsigned int* done, double* sse_dev, unsigned long long* rechecked,
+                               int grid, hipStream_t stream);
+bool fp32_mfma_enabled();
 // With `stop` (a solve's status word) the launch does nothing once the solve
 // is done; partial == nullptr leaves the objective out (labels only).
 bm_status launch_assign_mfma(const uint16_t* X, int64_t n, int d, const float* C,
