@@ -258,7 +258,7 @@ bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, con
  * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
  * kmeans_assign (labels and objective identical); it calls no hipMalloc,
  * hipFree or allocating library routine.  Its scratch (the flags, one FP64
- * partial per workgroup, a counter and the objective) is a fixed 64 KiB
+ * partial per workgroup and the objective) is a fixed 64 KiB
  * array in device memory that every GPU the library runs on holds until the
  * process ends; calls whose scratch would exceed it (k plus the workgroup
  * count of the call: about 7,000 workgroup partials with k <= 8,000) return

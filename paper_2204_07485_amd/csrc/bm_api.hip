@@ -251,7 +251,6 @@ static bm_status plan_solver(int d, int k, int64_t s, int64_t n_points, int grid
 struct SolverBuffers {
   SolverArgs a;
   double* partial = nullptr;      // final assignment pass: per-workgroup objective
-  unsigned int* done = nullptr;   //   arrival counter of its last-workgroup reduction
   double* sse_dev = nullptr;      //   the objective
   unsigned long long* rechecked = nullptr;  //   points recomputed on the FP32 path (MFMA form)
   size_t bytes = 0;
@@ -304,7 +303,6 @@ static void layout_solver(char* base, int64_t n, int64_t s, int d, int k, int T,
   a.deg_inc = deg;
   a.f_opt = fopt;
   b->partial = L.take<double>(final_grid > 0 ? final_grid : 1);
-  b->done = L.take<unsigned int>(1);
   b->sse_dev = L.take<double>(1);
   b->rechecked = L.take<unsigned long long>(1);
   b->bytes = L.off + 256;
@@ -325,7 +323,6 @@ static bm_status prepare_solver(hipStream_t stream, int64_t n, int64_t s, int d,
                 sbatch, b);
   BM_HIP(hipMemsetAsync(base, 0, b->ctrl_bytes, stream));
   if (final_grid > 0) {
-    BM_HIP(hipMemsetAsync(b->done, 0, sizeof(unsigned int), stream));
     BM_HIP(hipMemsetAsync(b->rechecked, 0, sizeof(unsigned long long), stream));
   }
   return BM_OK;
@@ -997,7 +994,7 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
     for (int round = 0; round <= o.max_iter && !done;) {
       for (int q = 0; q < kRoundsPerSync && round <= o.max_iter; ++q, ++round) {
         if ((st = launch_assign_mfma(m.p16, s, d, m.cw, m.degw, k, m.lab, nullptr, nullptr, nullptr,
-                                     nullptr, b.rechecked, mgrid, stream, &m.sv->status)) != BM_OK)
+                                     b.rechecked, mgrid, stream, &m.sv->status)) != BM_OK)
           return st;
         if (wave_rows) {
           if ((st = launch_labels_accum(m.p16, s, d, k, m.cw, m.lab, m.sv, m.partials, m.pcnt,
@@ -1052,10 +1049,9 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
   unsigned long long nrecheck = 0;
   if (final_pass) {
     BM_HIP(hipMemcpyAsync(b.a.deg_inc, deg_inc.data(), size_t(k), hipMemcpyHostToDevice, stream));
-    BM_HIP(hipMemsetAsync(b.done, 0, sizeof(unsigned int), stream));
     BM_HIP(hipMemsetAsync(b.rechecked, 0, sizeof(unsigned long long), stream));
     if ((st = launch_assign_mfma(static_cast<const uint16_t*>(X), n, d, centroids, b.a.deg_inc, k,
-                                 labels, nullptr, b.partial, b.done, b.sse_dev, b.rechecked, fgrid,
+                                 labels, nullptr, b.partial, b.sse_dev, b.rechecked, fgrid,
                                  stream)) != BM_OK)
       return st;
     BM_HIP(hipMemcpyAsync(&sse_host, b.sse_dev, sizeof(double), hipMemcpyDeviceToHost, stream));
@@ -1192,10 +1188,10 @@ bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int
   bm_status fst = BM_OK;
   if (final_mfma) {
     fst = launch_assign_mfma(static_cast<const uint16_t*>(X), n, d, a.Cinc, a.deg_inc, k, labels,
-                             nullptr, b.partial, b.done, b.sse_dev, b.rechecked, final_grid, stream);
+                             nullptr, b.partial, b.sse_dev, b.rechecked, final_grid, stream);
   } else if (final_pass) {
     fst = launch_assign(X, a.x_bf16, n, d, a.Cinc, a.deg_inc, k, labels, nullptr, b.partial,
-                        b.done, b.sse_dev, final_grid, stream);
+                        b.sse_dev, final_grid, stream);
   }
   BM_HIP(hipEventRecord(ev[2], stream));
   launch_lock.unlock();
@@ -1309,7 +1305,6 @@ bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, con
   if (mfma && (st = plan_assign_mfma(X, n, d, k, &grid)) != BM_OK) return st;
   uint8_t* deg_p = nullptr;
   double* partial_p = nullptr;
-  unsigned int* done_p = nullptr;
   double* sse_p = nullptr;
   unsigned long long* rechecked_p = nullptr;
   char* base = nullptr;
@@ -1318,7 +1313,6 @@ bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, con
     L.base = base;
     deg_p = L.take<uint8_t>(k);
     partial_p = L.take<double>(grid);
-    done_p = L.take<unsigned int>(1);
     sse_p = L.take<double>(1);
     rechecked_p = L.take<unsigned long long>(1);
     if (round == 0) {
@@ -1328,17 +1322,16 @@ bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, con
     }
   }
   if (deg) BM_HIP(hipMemcpyAsync(deg_p, deg, size_t(k), hipMemcpyHostToDevice, stream));
-  BM_HIP(hipMemsetAsync(done_p, 0, sizeof(unsigned int), stream));
   if (mfma) BM_HIP(hipMemsetAsync(rechecked_p, 0, sizeof(unsigned long long), stream));
   hipEvent_t ev[2] = {nullptr, nullptr};
   for (auto& e : ev) BM_HIP(hipEventCreate(&e));
   BM_HIP(hipEventRecord(ev[0], stream));
   if (mfma) {
     st = launch_assign_mfma(static_cast<const uint16_t*>(X), n, d, C, deg ? deg_p : nullptr, k,
-                            labels, min_d2, partial_p, done_p, sse_p, rechecked_p, grid, stream);
+                            labels, min_d2, partial_p, sse_p, rechecked_p, grid, stream);
   } else {
     st = launch_assign(X, o.x_dtype == BM_BF16, n, d, C, deg ? deg_p : nullptr, k, labels, min_d2,
-                       partial_p, done_p, sse_p, grid, stream);
+                       partial_p, sse_p, grid, stream);
   }
   if (st == BM_OK && hipEventRecord(ev[1], stream) != hipSuccess)
     st = set_error(BM_EDEVICE, "hipEventRecord failed");
@@ -1689,11 +1682,11 @@ static bm_status collective_run(const void* X, int64_t n, int32_t d, int32_t k, 
     BM_HIP(hipMemcpyAsync(b.a.deg_inc, deg_inc.data(), size_t(k), hipMemcpyHostToDevice, stream));
     if (final_mfma) {
       st = launch_assign_mfma(static_cast<const uint16_t*>(X), n, d, centroids, b.a.deg_inc, k,
-                              labels, nullptr, b.partial, b.done, b.sse_dev, b.rechecked, final_grid,
+                              labels, nullptr, b.partial, b.sse_dev, b.rechecked, final_grid,
                               stream);
     } else {
       st = launch_assign(X, o.x_dtype == BM_BF16, n, d, centroids, b.a.deg_inc, k, labels, nullptr,
-                         b.partial, b.done, b.sse_dev, final_grid, stream);
+                         b.partial, b.sse_dev, final_grid, stream);
     }
     if (st != BM_OK) return st;
     BM_HIP(hipMemcpyAsync(&sse_host, b.sse_dev, sizeof(double), hipMemcpyDeviceToHost, stream));

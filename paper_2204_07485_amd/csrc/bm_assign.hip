@@ -10,8 +10,9 @@
 // come through the scalar cache as SGPR operands.  The nearest centroid is chosen with FP32 direct
 // differences (FMA chain in dimension order; exact ties to the lowest index);
 // the chosen distance is then recomputed in FP64 for the objective.  Each workgroup
-// writes its FP64 partial objective; the last workgroup to finish adds the
-// partials in workgroup order, so the result does not depend on timing.
+// writes its FP64 partial objective and one more launch adds the partials in
+// workgroup order, so the result does not depend on timing (a fence and a
+// counter per workgroup to find the last one cost more than that launch).
 #include "bm_internal.h"
 
 namespace bm {
@@ -24,14 +25,12 @@ template <int DM, bool BF16>
 __global__ void __launch_bounds__(kAssignBlock)
     assign_kernel(const void* __restrict__ Xv, int64_t n, int d, const float* __restrict__ C,
                   const uint8_t* __restrict__ deg, int k, int32_t* __restrict__ labels,
-                  float* __restrict__ min_d2, double* __restrict__ partial,
-                  unsigned int* __restrict__ done, double* __restrict__ sse_out) {
+                  float* __restrict__ min_d2, double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   float* Cl = reinterpret_cast<float*>(lds_raw);
   int* act = reinterpret_cast<int*>(lds_raw + sizeof(float) * static_cast<size_t>(k) * DM);
   __shared__ int s_na;
   __shared__ double s_tmp[kAssignBlock / kWave + 1];
-  __shared__ int s_last;
 
   const int tid = threadIdx.x;
   for (int e = tid; e < k * DM; e += kAssignBlock) {
@@ -94,24 +93,9 @@ __global__ void __launch_bounds__(kAssignBlock)
     }
   }
   const double bsum = block_sum_f64<kAssignBlock>(sse, s_tmp);
-  if (tid == 0) {
-    partial[blockIdx.x] = bsum;
-    __threadfence();
-    const unsigned int prev = atomicAdd(done, 1u);
-    s_last = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (s_last) {  // the last workgroup adds the partials in a fixed order
-    __threadfence();
-    double v = 0.0;
-    for (unsigned int b = tid; b < gridDim.x; b += kAssignBlock)
-      v += __hip_atomic_load(&partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const double total = block_sum_f64<kAssignBlock>(v, s_tmp);
-    if (tid == 0) {
-      *sse_out = total;
-      __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  // the partials are added in workgroup order by sum_partials_kernel, launched
+  // after this kernel (no fence and atomic per workgroup)
+  if (tid == 0) partial[blockIdx.x] = bsum;
 }
 
 template <int DM>
@@ -151,8 +135,7 @@ int assign_grid(int64_t n, int d) {
 
 bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float* C,
                         const uint8_t* deg_dev, int k, int32_t* labels, float* min_d2,
-                        double* partial, unsigned int* done, double* sse_dev, int grid,
-                        hipStream_t stream) {
+                        double* partial, double* sse_dev, int grid, hipStream_t stream) {
   // FP32 rows at least 8 wide against at least 8 centroids with k d >= 1024
   // (below that the VALU scan is as fast): the matrix-core form (the same
   // labels, see bm_assign_mfma32.hip), on at most `grid` workgroups (the
@@ -161,7 +144,7 @@ bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float
     int mgrid = 0;
     if (plan_assign_mfma32(X, n, d, k, &mgrid) == BM_OK) {
       return launch_assign_mfma32(static_cast<const float*>(X), n, d, C, deg_dev, k, labels, min_d2,
-                                  partial, done, sse_dev, nullptr, mgrid < grid ? mgrid : grid, stream);
+                                  partial, sse_dev, nullptr, mgrid < grid ? mgrid : grid, stream);
     }
     clear_error();  // too large for its LDS plan: the VALU form below
   }
@@ -181,11 +164,31 @@ bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float
       return set_error(BM_EDEVICE, "assign LDS attribute: %s", hipGetErrorString(ea));
   }
   void* args[] = {const_cast<void**>(&X), &n, &d, const_cast<float**>(&C),
-                  const_cast<uint8_t**>(&deg_dev), &k, &labels, &min_d2, &partial, &done,
-                  &sse_dev};
+                  const_cast<uint8_t**>(&deg_dev), &k, &labels, &min_d2, &partial};
   const hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kAssignBlock), args, lds, stream);
   if (e != hipSuccess)
     return set_error(BM_EDEVICE, "assign launch failed: %s", hipGetErrorString(e));
+  return launch_sum_partials(partial, grid, sse_dev, stream);
+}
+
+namespace {
+// The objective: the workgroups' FP64 partials added in a fixed order (one
+// workgroup; each thread adds a strided subset, then a fixed tree).
+constexpr int kSumBlock = 256;
+__global__ void __launch_bounds__(kSumBlock)
+    sum_partials_kernel(const double* __restrict__ partial, int np, double* __restrict__ out) {
+  __shared__ double s_tmp[kSumBlock / kWave + 1];
+  double v = 0.0;
+  for (int g = threadIdx.x; g < np; g += kSumBlock) v += partial[g];
+  const double total = block_sum_f64<kSumBlock>(v, s_tmp);
+  if (threadIdx.x == 0) *out = total;
+}
+}  // namespace
+
+bm_status launch_sum_partials(const double* partial, int np, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kSumBlock), 0, stream, partial, np, out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(BM_EDEVICE, "objective sum launch failed: %s", hipGetErrorString(e));
   return BM_OK;
 }
 

@@ -202,8 +202,7 @@ __global__ void __launch_bounds__((block_for<KS, VEC>()))
     assign_mfma_kernel(const uint16_t* __restrict__ X, int64_t n, int d,
                        const float* __restrict__ C, const uint8_t* __restrict__ deg, int k,
                        int32_t* __restrict__ labels, float* __restrict__ min_d2,
-                       double* __restrict__ partial, unsigned int* __restrict__ done,
-                       double* __restrict__ sse_out, unsigned long long* __restrict__ rechecked,
+                       double* __restrict__ partial, unsigned long long* __restrict__ rechecked,
                        const int32_t* __restrict__ stop) {
   if (stop && *stop == kSolveDone) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -219,7 +218,6 @@ __global__ void __launch_bounds__((block_for<KS, VEC>()))
   constexpr int kNT = nt_for<KS, VEC>();
   __shared__ float s_cmax;
   __shared__ double s_tmp[kMfmaWaves + 1];
-  __shared__ int s_last;
   const int tid = threadIdx.x;
 
   // FP32 centroids (zero rows for inactive or padding slots)
@@ -439,24 +437,9 @@ __global__ void __launch_bounds__((block_for<KS, VEC>()))
   if (rechecked && nrecheck) atomicAdd(rechecked, nrecheck);
   if (!partial) return;
   const double bsum = block_sum_f64<kMfmaBlock>(sse, s_tmp);
-  if (tid == 0) {
-    partial[blockIdx.x] = bsum;
-    __threadfence();
-    const unsigned int prev = atomicAdd(done, 1u);
-    s_last = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (s_last) {  // the last workgroup adds the partials in a fixed order
-    __threadfence();
-    double v = 0.0;
-    for (unsigned int g = tid; g < gridDim.x; g += kMfmaBlock)
-      v += __hip_atomic_load(&partial[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const double total = block_sum_f64<kMfmaBlock>(v, s_tmp);
-    if (tid == 0) {
-      *sse_out = total;
-      __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  // the partials are added in workgroup order by sum_partials_kernel, launched
+  // after this kernel (no fence and atomic per workgroup)
+  if (tid == 0) partial[blockIdx.x] = bsum;
 }
 
 int mfma_ks(int d) { return d <= 32 ? 1 : d <= 64 ? 2 : d <= 128 ? 4 : 8; }
@@ -520,22 +503,21 @@ bm_status plan_assign_mfma(const void* X, int64_t n, int d, int k, int* grid) {
 
 bm_status launch_assign_mfma(const uint16_t* X, int64_t n, int d, const float* C,
                              const uint8_t* deg_dev, int k, int32_t* labels, float* min_d2,
-                             double* partial, unsigned int* done, double* sse_dev,
-                             unsigned long long* rechecked, int grid, hipStream_t stream,
-                             const int32_t* stop) {
+                             double* partial, double* sse_dev, unsigned long long* rechecked,
+                             int grid, hipStream_t stream, const int32_t* stop) {
   const int ks = mfma_ks(d);
   if (grid < 1 || n < 1 || d < 1 || d > 256 || k < 1 || k > 16 * kMaxCT)
     return set_error(BM_EINVAL, "MFMA assignment: bad plan");
   const void* fn = pick_mfma(ks, mfma_vec(X, d));
   const size_t lds = mfma_lds_plan(ks, k).total;
   void* args[] = {const_cast<uint16_t**>(&X), &n, &d, const_cast<float**>(&C),
-                  const_cast<uint8_t**>(&deg_dev), &k, &labels, &min_d2, &partial, &done,
-                  &sse_dev, &rechecked, const_cast<int32_t**>(&stop)};
+                  const_cast<uint8_t**>(&deg_dev), &k, &labels, &min_d2, &partial,
+                  &rechecked, const_cast<int32_t**>(&stop)};
   const hipError_t e =
       hipLaunchKernel(fn, dim3(grid), dim3(mfma_block(ks, mfma_vec(X, d))), args, lds, stream);
   if (e != hipSuccess)
     return set_error(BM_EDEVICE, "MFMA assign launch failed: %s", hipGetErrorString(e));
-  return BM_OK;
+  return partial ? launch_sum_partials(partial, grid, sse_dev, stream) : BM_OK;
 }
 
 }  // namespace bm

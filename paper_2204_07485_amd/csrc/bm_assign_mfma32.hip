@@ -138,7 +138,6 @@ __global__ void __launch_bounds__(kMfma32Block)
     assign_mfma32_kernel(const float* __restrict__ X, int64_t n, int d, const float* __restrict__ C,
                          const uint8_t* __restrict__ deg, int k, int32_t* __restrict__ labels,
                          float* __restrict__ min_d2, double* __restrict__ partial,
-                         unsigned int* __restrict__ done, double* __restrict__ sse_out,
                          unsigned long long* __restrict__ rechecked) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const Mfma32Lds P = mfma32_lds_plan(NQ, k);
@@ -152,7 +151,6 @@ __global__ void __launch_bounds__(kMfma32Block)
   constexpr int kNT = nt32_for<NQ>();
   __shared__ float s_cmax;
   __shared__ double s_tmp[kWaves + 1];
-  __shared__ int s_last;
   const int tid = threadIdx.x;
 
   // FP32 centroids (zero rows for inactive or padding slots)
@@ -360,24 +358,9 @@ __global__ void __launch_bounds__(kMfma32Block)
   }
   if (rechecked && nrecheck) atomicAdd(rechecked, nrecheck);
   const double bsum = block_sum_f64<kMfma32Block>(sse, s_tmp);
-  if (tid == 0) {
-    partial[blockIdx.x] = bsum;
-    __threadfence();
-    const unsigned int prev = atomicAdd(done, 1u);
-    s_last = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (s_last) {  // the last workgroup adds the partials in a fixed order
-    __threadfence();
-    double v = 0.0;
-    for (unsigned int g = tid; g < gridDim.x; g += kMfma32Block)
-      v += __hip_atomic_load(&partial[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const double total = block_sum_f64<kMfma32Block>(v, s_tmp);
-    if (tid == 0) {
-      *sse_out = total;
-      __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  // the partials are added in workgroup order by sum_partials_kernel, launched
+  // after this kernel (no fence and atomic per workgroup)
+  if (tid == 0) partial[blockIdx.x] = bsum;
 }
 
 int mfma32_nq(int d) {
@@ -441,20 +424,19 @@ bm_status plan_assign_mfma32(const void* X, int64_t n, int d, int k, int* grid) 
 
 bm_status launch_assign_mfma32(const float* X, int64_t n, int d, const float* C, const uint8_t* deg_dev,
                                int k, int32_t* labels, float* min_d2, double* partial,
-                               unsigned int* done, double* sse_dev, unsigned long long* rechecked,
-                               int grid, hipStream_t stream) {
+                               double* sse_dev, unsigned long long* rechecked, int grid,
+                               hipStream_t stream) {
   const int nq = mfma32_nq(d);
   if (grid < 1 || n < 1 || d < 1 || d > 256 || k < 1 || k > 16 * kMaxCT32)
     return set_error(BM_EINVAL, "FP32 MFMA assignment: bad plan");
   const void* fn = pick_mfma32(nq, mfma32_vec(X, d));
   const size_t lds = mfma32_lds_plan(nq, k).total;
   void* args[] = {const_cast<float**>(&X), &n, &d, const_cast<float**>(&C),
-                  const_cast<uint8_t**>(&deg_dev), &k, &labels, &min_d2, &partial, &done,
-                  &sse_dev, &rechecked};
+                  const_cast<uint8_t**>(&deg_dev), &k, &labels, &min_d2, &partial, &rechecked};
   const hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kMfma32Block), args, lds, stream);
   if (e != hipSuccess)
     return set_error(BM_EDEVICE, "FP32 MFMA assign launch failed: %s", hipGetErrorString(e));
-  return BM_OK;
+  return launch_sum_partials(partial, grid, sse_dev, stream);
 }
 
 }  // namespace bm

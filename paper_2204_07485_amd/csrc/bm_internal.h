@@ -173,9 +173,10 @@ bm_status max_lds_per_block(size_t* bytes);
 
 bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float* C,
                         const uint8_t* deg_dev, int k, int32_t* labels, float* min_d2,
-                        double* partial, unsigned int* done, double* sse_dev, int grid,
-                        hipStream_t stream);
+                        double* partial, double* sse_dev, int grid, hipStream_t stream);
 int assign_grid(int64_t n, int d);
+// *out = the np partials added in a fixed order (one workgroup).
+bm_status launch_sum_partials(const double* partial, int np, double* out, hipStream_t stream);
 
 // Batched Lloyd (bm_batch.hip): per-solve state, laid out in device memory.
 constexpr int kSolveRunning = 0;  // next round: assignment + update
@@ -238,15 +239,15 @@ bm_status plan_assign_mfma(const void* X, int64_t n, int d, int k, int* grid);
 bm_status plan_assign_mfma32(const void* X, int64_t n, int d, int k, int* grid);
 bm_status launch_assign_mfma32(const float* X, int64_t n, int d, const float* C, const uint8_t* deg_dev,
                                int k, int32_t* labels, float* min_d2, double* partial,
-                               unsigned int* done, double* sse_dev, unsigned long long* rechecked,
-                               int grid, hipStream_t stream);
+                               double* sse_dev, unsigned long long* rechecked, int grid,
+                               hipStream_t stream);
 bool fp32_mfma_enabled();
 // With `stop` (a solve's status word) the launch does nothing once the solve
 // is done; partial == nullptr leaves the objective out (labels only).
 bm_status launch_assign_mfma(const uint16_t* X, int64_t n, int d, const float* C,
                              const uint8_t* deg_dev, int k, int32_t* labels, float* min_d2,
-                             double* partial, unsigned int* done, double* sse_dev,
-                             unsigned long long* rechecked, int grid, hipStream_t stream,
+                             double* partial, double* sse_dev, unsigned long long* rechecked,
+                             int grid, hipStream_t stream,
                              const int32_t* stop = nullptr);
 
 }  // namespace bm

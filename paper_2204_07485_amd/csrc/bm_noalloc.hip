@@ -1,8 +1,8 @@
 // bm_noalloc.hip -- kmeans_assign_noalloc: the assignment step and objective
 // of kmeans_assign (Sec. 2, Eq. (1)) for callers that cannot allocate device
 // memory.  Its scratch (the degenerate flags, per-workgroup partial
-// objectives, the last-workgroup counter, the objective and the recheck
-// count) lives in a fixed static device array instead of the library's
+// objectives, the objective and the recheck count) lives in a fixed static
+// device array instead of the library's
 // growing pool; the kernels are the ones kmeans_assign launches.
 //
 // The array is a host-side stand-in in host code: its device address is taken
@@ -37,13 +37,10 @@ bm_status scratch_address(int dev, unsigned char** out) {
   return BM_OK;
 }
 
-// Clears the last-workgroup counter and the recheck count (a kernel rather
-// than a memset, so the call is safe inside a caller's graph capture).
-__global__ void noalloc_clear_kernel(unsigned int* done, unsigned long long* rechecked) {
-  if (threadIdx.x == 0) {
-    *done = 0u;
-    *rechecked = 0ull;
-  }
+// Clears the recheck count (a kernel rather than a memset, so the call is
+// safe inside a caller's graph capture).
+__global__ void noalloc_clear_kernel(unsigned long long* rechecked) {
+  if (threadIdx.x == 0) *rechecked = 0ull;
 }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -82,11 +79,10 @@ extern "C" bm_status kmeans_assign_noalloc(const void* X, int64_t n, int32_t d, 
 
   int grid = assign_grid(n, d);
   if (mfma && (st = plan_assign_mfma(X, n, d, k, &grid)) != BM_OK) return st;
-  // layout: flags | partials | counter | objective | recheck count
+  // layout: flags | partials | objective | recheck count
   const size_t off_deg = 0;
   const size_t off_part = align256(off_deg + static_cast<size_t>(k));
-  const size_t off_done = align256(off_part + sizeof(double) * static_cast<size_t>(grid));
-  const size_t off_sse = off_done + 64;
+  const size_t off_sse = align256(off_part + sizeof(double) * static_cast<size_t>(grid));
   const size_t off_rechk = off_sse + 64;
   const size_t need = off_rechk + 64;
   if (need > kNoAllocScratchBytes)
@@ -95,7 +91,6 @@ extern "C" bm_status kmeans_assign_noalloc(const void* X, int64_t n, int32_t d, 
                      "its fixed scratch holds %zu B", need, k, grid, kNoAllocScratchBytes);
   uint8_t* deg_p = base + off_deg;
   double* partial_p = reinterpret_cast<double*>(base + off_part);
-  unsigned int* done_p = reinterpret_cast<unsigned int*>(base + off_done);
   double* sse_p = reinterpret_cast<double*>(base + off_sse);
   unsigned long long* rechecked_p = reinterpret_cast<unsigned long long*>(base + off_rechk);
 
@@ -103,15 +98,15 @@ extern "C" bm_status kmeans_assign_noalloc(const void* X, int64_t n, int32_t d, 
     const hipError_t e = hipMemcpyAsync(deg_p, deg, size_t(k), hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return set_error(BM_EDEVICE, "flag copy failed: %s", hipGetErrorString(e));
   }
-  hipLaunchKernelGGL(noalloc_clear_kernel, dim3(1), dim3(64), 0, stream, done_p, rechecked_p);
+  hipLaunchKernelGGL(noalloc_clear_kernel, dim3(1), dim3(64), 0, stream, rechecked_p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(BM_EDEVICE, "clear launch failed: %s", hipGetErrorString(e));
   if (mfma) {
     st = launch_assign_mfma(static_cast<const uint16_t*>(X), n, d, C, deg ? deg_p : nullptr, k,
-                            labels, min_d2, partial_p, done_p, sse_p, rechecked_p, grid, stream);
+                            labels, min_d2, partial_p, sse_p, rechecked_p, grid, stream);
   } else {
     st = launch_assign(X, o.x_dtype == BM_BF16, n, d, C, deg ? deg_p : nullptr, k, labels, min_d2,
-                       partial_p, done_p, sse_p, grid, stream);
+                       partial_p, sse_p, grid, stream);
   }
   if (st != BM_OK) return st;
   double v = 0.0;
