@@ -31,8 +31,8 @@ COUNTERS = os.path.join(ROOT, "profiles", "solver_medium_hbm_counters.md")
 
 # the sources that define the profiled kernels (the persistent solver and the
 # FP32 final pass) and how they are launched
-PROFILED_SOURCES = ("bm_api.hip", "bm_solver.hip", "bm_assign.hip", "bm_device.h", "bm_internal.h",
-                    "bm_rng.h")
+PROFILED_SOURCES = ("bm_api.hip", "bm_solver.hip", "bm_assign.hip", "bm_assign_mfma32.hip",
+                    "bm_device.h", "bm_internal.h", "bm_rng.h")
 
 
 def source_hash():
@@ -254,16 +254,16 @@ def final_passes(Xmed, gold, reps=5):
             warm.append(bigmeans.last_assign_ms())
         ms = statistics.median(vals)
         algo = n * d * 4 + n * 4
-        # k d >= 1024 (and d, k >= 8) runs on the matrix cores (same labels)
-        mfma = d >= 8 and k >= 8 and k * d >= 1024
-        kernel = (f"assign_mfma32_kernel<{ {68: 5, 128: 8}[d] },true>" if mfma
+        # k d >= 256 (and d, k >= 8) runs on the matrix cores (same labels)
+        mfma = d >= 8 and k >= 8 and k * d >= 256
+        kernel = (f"assign_mfma32_kernel<{ {16: 1, 68: 5, 128: 8}[d] },true>" if mfma
                   else f"assign_kernel<{ {16: 16, 68: 72}[d] },f32>")
         res[name] = {"kernel": kernel, "ms_cold": ms,
                      "ms_warm": statistics.median(warm), "algorithmic_bytes": algo,
                      "gbs_cold": algo / (ms * 1e-3) / 1e9, "hbm_frac_cold": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "tflops_cold": 2 * n * k * d / (ms * 1e-3) / 1e12}
         if mfma:  # issued matrix work: k padded to 16-row tiles, d to 16-column chunks
-            kp, dp = 16 * -(-k // 16), 16 * { 68: 5, 128: 8}[d]
+            kp, dp = 16 * -(-k // 16), 16 * {16: 1, 68: 5, 128: 8}[d]
             res[name]["mfma_tflops_cold"] = 2 * n * kp * dp / (ms * 1e-3) / 1e12
             res[name]["mfma_frac_cold"] = res[name]["mfma_tflops_cold"] / FP32_MFMA_PEAK_TFLOPS
     del Xw, flush
@@ -481,7 +481,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_solver,
                      "ms_per_launch": solver_ms, "algorithmic_bytes": solver_bytes,
                      "tflops": solver_flops / (solver_ms * 1e-3) / 1e12},
-        "roofline_final_pass": {"bound": "hbm", "kernel": "assign_kernel<16,f32>",
+        "roofline_final_pass": {"bound": "hbm", "kernel": "assign_mfma32_kernel<1,true>",
                                 "achieved": final_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": final_gbs / HBM_PEAK_GBS, "traffic": traffic_final,
                                 "ms_per_launch": final_ms,

@@ -30,7 +30,7 @@ int32_t bm_debug_mfma_lloyd(int32_t on);
 
 /* FP32 points: 1 (default) lets the full-data assignment (final pass,
  * kmeans_assign) run on the matrix cores when d >= 8, k >= 8 and
- * k d >= 1024, 0 keeps it
+ * k d >= 256, 0 keeps it
  * on the VALU direct-difference kernel (both give the same labels).  Returns
  * the previous setting, or -1 for another value.  Process-wide. */
 int32_t bm_debug_fp32_mfma(int32_t on);

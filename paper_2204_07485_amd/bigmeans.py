@@ -580,7 +580,7 @@ def debug_counters():
 
 def debug_fp32_mfma(on):
     """FP32 full-data assignment: 1 = on the matrix cores when d >= 8,
-    k >= 8 and k d >= 1024 (default), 0 = on the VALU kernel; returns the
+    k >= 8 and k d >= 256 (default), 0 = on the VALU kernel; returns the
     previous value."""
     L = load()
     L.bm_debug_fp32_mfma.argtypes = [ct.c_int32]

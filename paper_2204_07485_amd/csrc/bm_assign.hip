@@ -136,11 +136,11 @@ int assign_grid(int64_t n, int d) {
 bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float* C,
                         const uint8_t* deg_dev, int k, int32_t* labels, float* min_d2,
                         double* partial, double* sse_dev, int grid, hipStream_t stream) {
-  // FP32 rows at least 8 wide against at least 8 centroids with k d >= 1024
+  // FP32 rows at least 8 wide against at least 8 centroids with k d >= 256
   // (below that the VALU scan is as fast): the matrix-core form (the same
   // labels, see bm_assign_mfma32.hip), on at most `grid` workgroups (the
   // caller's partial buffer)
-  if (!x_bf16 && d >= 8 && k >= 8 && k * d >= 1024 && fp32_mfma_enabled()) {
+  if (!x_bf16 && d >= 8 && k >= 8 && k * d >= 256 && fp32_mfma_enabled()) {
     int mgrid = 0;
     if (plan_assign_mfma32(X, n, d, k, &mgrid) == BM_OK) {
       return launch_assign_mfma32(static_cast<const float*>(X), n, d, C, deg_dev, k, labels, min_d2,

@@ -1,5 +1,5 @@
 """GPU parity of the FP32 matrix-core assignment (the full-data pass for FP32
-X with d >= 8, k >= 8 and k d >= 1024; every case below meets that).
+X with d >= 8, k >= 8 and k d >= 256; every case below meets that).
 
 Its labels must equal the VALU FP32 direct-difference kernel's bit for bit
 (the error band and the FP32 recheck make them so; the test hook
