@@ -363,6 +363,284 @@ __global__ void __launch_bounds__(kMfma32Block)
   if (tid == 0) partial[blockIdx.x] = bsum;
 }
 
+// The batched Lloyd assignment (the work list, solve states and accumulation
+// of batch_assign_kernel in bm_batch.hip) with the labels from the matrix
+// cores: rows are the zero-padded copies (row stride dm = padded d), a
+// workgroup stages each solve's centroids (FP32 rows, the lane-layout operand
+// tiles, norms and flags) when its tile list reaches the solve, and for every
+// labelled row the point's four lanes add their coordinates' FP64 values to
+// the solve's cluster sums and their FP64 squared differences to the tile's
+// objective, so sums, counts and objectives are those of the VALU kernel up
+// to the association of FP64 sums.
+constexpr int kBM32Block = 256;
+
+template <int NQ, bool SUMS_LDS>
+__global__ void __launch_bounds__(kBM32Block)
+    batch_assign_mfma32_kernel(const float* __restrict__ Pp, int dm, int d, const float* __restrict__ C,
+                               const uint8_t* __restrict__ deg, const BatchSolve* __restrict__ sv,
+                               const int32_t* __restrict__ tile_solve, int ntiles, int tile_rows,
+                               int kmax, double* __restrict__ sums, int32_t* __restrict__ cnt,
+                               double* __restrict__ tile_f, int32_t* __restrict__ labels, int dry) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const Mfma32Lds P = mfma32_lds_plan(NQ, kmax);
+  const int ldc = P.ldc;
+  const int lds_ld = dm + 1;  // cluster-sum row stride in LDS (odd)
+  float* atile = reinterpret_cast<float*>(lds_raw + P.atile);
+  float* c32 = reinterpret_cast<float*>(lds_raw + P.c32);
+  float* cnorm = reinterpret_cast<float*>(lds_raw + P.cnorm);
+  int* act = reinterpret_cast<int*>(lds_raw + P.act);
+  int* cnt_l = act + P.kp;
+  double* sums_l = reinterpret_cast<double*>(lds_raw + ((P.total + sizeof(int) * P.kp + 15) & ~size_t(15)));
+  constexpr int kWaves = kBM32Block / kWave;
+  constexpr int kNT = nt32_for<NQ>();
+  __shared__ int s_j, s_k, s_c0, s_status, s_tile0;
+  __shared__ int64_t s_row0, s_s;
+  __shared__ float s_cmax;
+  __shared__ double s_tmp[kWaves + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int col = lane & 15;
+  const int grp = lane >> 4;
+  const float dd = static_cast<float>(d);
+  const float kE1 = (2.f * dd + 8.f) * 0x1.0p-24f;
+  const float kF = (dd + 3.f) * 0x1.0p-24f;
+
+  int cur = -1;          // solve whose centroids are staged
+  bool cur_acc = false;  // ... and whose sums are being accumulated
+  int cur_k = 0, cur_c0 = 0;
+  auto flush = [&]() {  // this workgroup's LDS sums and counts of solve `cur`
+    __syncthreads();
+    if (SUMS_LDS) {
+      for (int e = tid; e < cur_k * d; e += kBM32Block) {
+        const int j = e / d;
+        const int t = e - j * d;
+        if (cnt_l[j]) unsafeAtomicAdd(&sums[static_cast<size_t>(cur_c0 + j) * dm + t], sums_l[j * lds_ld + t]);
+      }
+    }
+    for (int j = tid; j < cur_k; j += kBM32Block)
+      if (cnt_l[j]) atomicAdd(&cnt[cur_c0 + j], cnt_l[j]);
+    __syncthreads();
+  };
+
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    if (tid == 0) {
+      const int j = tile_solve[t];
+      const BatchSolve S = sv[j];
+      s_j = j;
+      s_k = S.k;
+      s_c0 = S.c0;
+      s_status = S.status;
+      s_tile0 = S.tile0;
+      s_row0 = S.row0;
+      s_s = S.s;
+    }
+    __syncthreads();
+    const int status = s_status;
+    if (status == kSolveDone) {
+      __syncthreads();
+      continue;
+    }
+    const int k = s_k;
+    const int c0 = s_c0;
+    const int CT = (k + 15) / 16;
+    const bool accumulate = status == kSolveRunning && !dry;
+    if (s_j != cur) {
+      if (cur_acc) flush();
+      cur = s_j;
+      cur_acc = accumulate;
+      cur_k = k;
+      cur_c0 = c0;
+      const int kp = 16 * CT;
+      for (int e = tid; e < kp * 16 * NQ; e += kBM32Block) {
+        const int m = e / (16 * NQ);
+        const int tt = e - m * (16 * NQ);
+        const bool live = m < k && !deg[c0 + m];
+        c32[m * ldc + tt] = (live && tt < d) ? C[static_cast<size_t>(c0 + m) * d + tt] : 0.f;
+      }
+      for (int j = tid; j < kp; j += kBM32Block) cnt_l[j] = 0;
+      if (SUMS_LDS && accumulate)
+        for (int e = tid; e < k * lds_ld; e += kBM32Block) sums_l[e] = 0.0;
+      __syncthreads();
+      for (int e = tid; e < CT * NQ * 4 * 64; e += kBM32Block) {
+        const int ln = e & 63;
+        const int ins = e >> 6;
+        const int kk = ins & 3;
+        const int q = (ins >> 2) % NQ;
+        const int ct = (ins >> 2) / NQ;
+        atile[e] = c32[(16 * ct + (ln & 15)) * ldc + 16 * q + 4 * (ln >> 4) + kk];
+      }
+      for (int m = tid; m < kp; m += kBM32Block) {
+        const bool live = m < k && !deg[c0 + m];
+        double acc = 0.0;
+        for (int tt = 0; tt < d; ++tt) {
+          const double c = c32[m * ldc + tt];
+          acc += c * c;
+        }
+        cnorm[m] = live ? static_cast<float>(acc) : __builtin_inff();
+        act[m] = live ? 1 : 0;
+      }
+      __syncthreads();
+      if (tid < kWave) {
+        float v = 0.f;
+        for (int m = tid; m < kp; m += kWave)
+          if (act[m]) v = fmaxf(v, sqrtf(cnorm[m]));
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+        if (tid == 0) s_cmax = v * 1.0001f;
+      }
+      __syncthreads();
+    }
+    const float cmax = s_cmax;
+    const float kE2 = 3.f * 0x1.0p-24f * cmax * cmax;
+    const int64_t r0 = s_row0 + static_cast<int64_t>(t - s_tile0) * tile_rows;
+    const int64_t rend = s_row0 + s_s;
+    const int64_t r1 = r0 + tile_rows < rend ? r0 + tile_rows : rend;
+    const int64_t nsteps = (r1 - r0 + 16 * kNT - 1) / (16 * kNT);
+    double* sums_dst = SUMS_LDS ? sums_l : sums + static_cast<size_t>(c0) * dm;
+    const int sld = SUMS_LDS ? lds_ld : dm;
+    double f = 0.0;
+    for (int64_t step = wave; step < nsteps; step += kWaves) {
+      float4 b[kNT][NQ];
+#pragma unroll
+      for (int nt = 0; nt < kNT; ++nt) {
+        const int64_t i = r0 + step * (16 * kNT) + 16 * nt + col;
+        const float* row = Pp + static_cast<size_t>(i < r1 ? i : r1 - 1) * dm;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int t0 = 16 * q + 4 * grp;
+          const bool in = t0 < dm;  // rows are dm wide (a multiple of 4), zero padded past d
+          const float4 v = *reinterpret_cast<const float4*>(row + (in ? t0 : 0));
+          b[nt][q] = in ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      }
+      float b1[kNT], b2[kNT];
+      int j1[kNT];
+#pragma unroll
+      for (int nt = 0; nt < kNT; ++nt) {
+        b1[nt] = __builtin_inff();
+        b2[nt] = __builtin_inff();
+        j1[nt] = -1;
+      }
+      for (int ct = 0; ct < CT; ++ct) {
+        f32x4v acc[kNT];
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) acc[nt] = f32x4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const float a = atile[((ct * NQ + q) * 4 + kk) * 64 + lane];
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt)
+              acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, f4_at(b[nt][q], kk), acc[nt], 0, 0, 0);
+          }
+        }
+        const float4 cn = *reinterpret_cast<const float4*>(cnorm + 16 * ct + 4 * grp);
+        const float cnq[4] = {cn.x, cn.y, cn.z, cn.w};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = 16 * ct + 4 * grp + r;
+#pragma unroll
+          for (int nt = 0; nt < kNT; ++nt) {
+            const float e = __builtin_fmaf(-2.0f, acc[nt][r], cnq[r]);
+            const bool lt = e < b1[nt];
+            j1[nt] = lt ? m : j1[nt];
+            b2[nt] = __builtin_amdgcn_fmed3f(b1[nt], b2[nt], e);
+            b1[nt] = lt ? e : b1[nt];
+          }
+        }
+      }
+#pragma unroll
+      for (int nt = 0; nt < kNT; ++nt) {
+        const int64_t i = r0 + step * (16 * kNT) + 16 * nt + col;
+        const bool valid = i < r1;
+#pragma unroll
+        for (int off = 16; off <= 32; off <<= 1) {
+          const float ob1 = __shfl_xor(b1[nt], off, kWave);
+          const float ob2 = __shfl_xor(b2[nt], off, kWave);
+          const int oj1 = __shfl_xor(j1[nt], off, kWave);
+          const bool other = ob1 < b1[nt] ||
+                             (ob1 == b1[nt] && static_cast<unsigned>(oj1) < static_cast<unsigned>(j1[nt]));
+          b2[nt] = other ? fminf(b1[nt], ob2) : fminf(b2[nt], ob1);
+          b1[nt] = other ? ob1 : b1[nt];
+          j1[nt] = other ? oj1 : j1[nt];
+        }
+        int w = j1[nt];
+        float xx = 0.f;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) xx = __builtin_fmaf(f4_at(b[nt][q], u), f4_at(b[nt][q], u), xx);
+        xx += __shfl_xor(xx, 16, kWave);
+        xx += __shfl_xor(xx, 32, kWave);
+        const float xn = sqrtf(xx) * 1.001f;
+        const float band = 2.02f * (kE1 * xn * cmax + kE2 + kF * (xn + cmax) * (xn + cmax));
+        const bool rchk = valid && !(b2[nt] - b1[nt] > band);
+        if (__ballot(rchk)) {
+          // the FP32 path's distance to every active centroid (see the
+          // full-data kernel above)
+          const float* xr = Pp + static_cast<size_t>(valid ? i : r0) * dm;
+          float best = __builtin_inff();
+          int bj = -1;
+          if (rchk) {
+            for (int ct = 0; ct < CT; ++ct) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int m = 16 * ct + 4 * grp + r;
+                if (act[m]) {
+                  const float v = fp32_row_dist<true>(xr, d, c32 + m * ldc);
+                  const float key = v == v ? v : __builtin_inff();
+                  if (bj < 0 || key < best) {
+                    best = key;
+                    bj = m;
+                  }
+                }
+              }
+            }
+          }
+#pragma unroll
+          for (int off = 16; off <= 32; off <<= 1) {
+            const float ob = __shfl_xor(best, off, kWave);
+            const int oj = __shfl_xor(bj, off, kWave);
+            if (oj >= 0 && (bj < 0 || ob < best ||
+                            (ob == best && static_cast<unsigned>(oj) < static_cast<unsigned>(bj)))) {
+              best = ob;
+              bj = oj;
+            }
+          }
+          if (rchk) w = bj;
+        }
+        if (valid && w >= 0) {
+          if (labels && !dry && grp == 0) labels[i] = w;
+          // the winner's FP64 squared distance (this lane's columns) and,
+          // when accumulating, the FP64 cluster sums and the count
+          const float* cw = c32 + w * ldc;
+          double part = 0.0;
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const float4 cv = *reinterpret_cast<const float4*>(cw + 16 * q + 4 * grp);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int tc = 16 * q + 4 * grp + u;
+              const double xv = static_cast<double>(f4_at(b[nt][q], u));
+              const double e = xv - static_cast<double>(f4_at(cv, u));
+              part = __builtin_fma(e, e, part);
+              if (accumulate && tc < d) unsafeAtomicAdd(sums_dst + w * sld + tc, xv);
+            }
+          }
+          f += part;
+          if (accumulate && grp == 0) atomicAdd(&cnt_l[w], 1);
+        }
+      }
+    }
+    const double ft = block_sum_f64<kBM32Block>(f, s_tmp);
+    if (tid == 0) tile_f[t] = ft;
+    __syncthreads();
+  }
+  if (cur_acc) flush();
+}
+
 int mfma32_nq(int d) {
   return d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 4 : d <= 80 ? 5 : d <= 128 ? 8 : 16;
 }
@@ -437,6 +715,64 @@ bm_status launch_assign_mfma32(const float* X, int64_t n, int d, const float* C,
   if (e != hipSuccess)
     return set_error(BM_EDEVICE, "FP32 MFMA assign launch failed: %s", hipGetErrorString(e));
   return launch_sum_partials(partial, grid, sse_dev, stream);
+}
+
+size_t batch_assign_mfma32_lds(int d, int kmax, bool sums_lds) {
+  if (d < 1 || d > 256 || kmax < 1 || kmax > 16 * kMaxCT32) return ~size_t(0);
+  const Mfma32Lds P = mfma32_lds_plan(mfma32_nq(d), kmax);
+  size_t b = (P.total + sizeof(int) * P.kp + 15) & ~size_t(15);
+  if (sums_lds) b += sizeof(double) * static_cast<size_t>(kmax) * (padded_dim(d) + 1);
+  return b;
+}
+
+namespace {
+template <int NQ, bool SUMS_LDS>
+const void* bm32_fn() {
+  return reinterpret_cast<const void*>(&batch_assign_mfma32_kernel<NQ, SUMS_LDS>);
+}
+template <bool SUMS_LDS>
+const void* pick_bm32(int nq) {
+  switch (nq) {
+    case 1: return bm32_fn<1, SUMS_LDS>();
+    case 2: return bm32_fn<2, SUMS_LDS>();
+    case 4: return bm32_fn<4, SUMS_LDS>();
+    case 5: return bm32_fn<5, SUMS_LDS>();
+    case 8: return bm32_fn<8, SUMS_LDS>();
+    case 16: return bm32_fn<16, SUMS_LDS>();
+    default: return nullptr;
+  }
+}
+}  // namespace
+
+bm_status launch_batch_assign_mfma32(const float* Pp, int d, const float* C, const uint8_t* deg,
+                                     const BatchSolve* sv, const int32_t* tile_solve, int ntiles,
+                                     int tile_rows, int kmax, bool sums_lds, double* sums,
+                                     int32_t* cnt, double* tile_f, int32_t* labels, int dry,
+                                     hipStream_t stream) {
+  const int nq = mfma32_nq(d);
+  const void* fn = sums_lds ? pick_bm32<true>(nq) : pick_bm32<false>(nq);
+  const size_t lds = batch_assign_mfma32_lds(d, kmax, sums_lds);
+  if (!fn || lds == ~size_t(0)) return set_error(BM_EINVAL, "batched FP32 MFMA assignment: bad plan");
+  static_assert(kBM32Block == 256, "one workgroup size for the plan below");
+  if (lds > 65536 &&
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+    return set_error(BM_ENOTSUP, "cannot reserve %zu B of LDS for the batched FP32 MFMA assignment", lds);
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBM32Block, lds) != hipSuccess || per_cu < 1)
+    return set_error(BM_EDEVICE, "cannot plan the batched FP32 MFMA assignment");
+  int grid = cus * per_cu;
+  if (grid > ntiles) grid = ntiles;
+  if (grid < 1) return BM_OK;
+  int dm = padded_dim(d);
+  void* args[] = {const_cast<float**>(&Pp), &dm, &d, const_cast<float**>(&C), const_cast<uint8_t**>(&deg),
+                  const_cast<BatchSolve**>(&sv), const_cast<int32_t**>(&tile_solve), &ntiles, &tile_rows,
+                  &kmax, &sums, &cnt, &tile_f, &labels, &dry};
+  const hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kBM32Block), args, lds, stream);
+  if (e != hipSuccess)
+    return set_error(BM_EDEVICE, "batched FP32 MFMA assign launch failed: %s", hipGetErrorString(e));
+  return BM_OK;
 }
 
 }  // namespace bm

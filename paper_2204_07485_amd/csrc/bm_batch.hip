@@ -715,6 +715,17 @@ bm_status launch_batch_assign(const float* Pp, int d, const float* C, const floa
                               int32_t* cnt, double* tile_f, int32_t* labels, int dry, int grid,
                               hipStream_t stream, const int32_t* labels_in, double* partials,
                               int32_t* pcnt) {
+  // rows at least 8 wide and up to 128 centroids per solve with kmax d >= 256:
+  // labels from the matrix cores (the same labels, sums, counts and
+  // objectives up to FP64 association), when its larger LDS plan fits
+  if (!labels_in && !partials && d >= 8 && kmax >= 8 && kmax <= 128 && kmax * d >= 256 &&
+      fp32_mfma_enabled()) {
+    size_t lds_max = 0;
+    if (max_lds_per_block(&lds_max) == BM_OK && batch_assign_mfma32_lds(d, kmax, sums_lds) + 1024 <= lds_max)
+      return launch_batch_assign_mfma32(Pp, d, C, deg, sv, tile_solve, ntiles, tile_rows, kmax, sums_lds,
+                                        sums, cnt, tile_f, labels, dry, stream);
+    clear_error();
+  }
   const void* fn = sums_lds ? pick_batch_assign<true>(padded_dim(d)) : pick_batch_assign<false>(padded_dim(d));
   if (!fn || grid < 1) return set_error(BM_EINVAL, "batched assignment: bad plan");
   if (partials && ntiles > grid)

@@ -242,6 +242,14 @@ bm_status launch_assign_mfma32(const float* X, int64_t n, int d, const float* C,
                                double* sse_dev, unsigned long long* rechecked, int grid,
                                hipStream_t stream);
 bool fp32_mfma_enabled();
+// The batched assignment with matrix-core labels (same results as
+// launch_batch_assign's kernel; no labels_in / partial-block modes).
+size_t batch_assign_mfma32_lds(int d, int kmax, bool sums_lds);
+bm_status launch_batch_assign_mfma32(const float* Pp, int d, const float* C, const uint8_t* deg,
+                                     const BatchSolve* sv, const int32_t* tile_solve, int ntiles,
+                                     int tile_rows, int kmax, bool sums_lds, double* sums,
+                                     int32_t* cnt, double* tile_f, int32_t* labels, int dry,
+                                     hipStream_t stream);
 // With `stop` (a solve's status word) the launch does nothing once the solve
 // is done; partial == nullptr leaves the objective out (labels only).
 bm_status launch_assign_mfma(const uint16_t* X, int64_t n, int d, const float* C,
