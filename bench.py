@@ -77,6 +77,8 @@ def parse():
                     help="skip the BF16 workload's mixed-precision (MFMA) comparison")
     ap.add_argument("--no-final", action="store_true",
                     help="skip the cache-flushed final-pass timings")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the collective-mode and sample-size-sweep section (for profiling the headline)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a plain 1 GiB device copy three times (a known "
                          "amount of HBM traffic for scaling profiler byte counters)")
@@ -500,8 +502,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    print("collective mode and sample-size sweep ...", file=sys.stderr, flush=True)
-    line.update(collective_and_sweep(Xd, W))
+    if not args.no_extras:
+        print("collective mode and sample-size sweep ...", file=sys.stderr, flush=True)
+        line.update(collective_and_sweep(Xd, W))
     if not args.no_final:
         print("final passes (cache flushed) ...", file=sys.stderr, flush=True)
         line["final_pass"] = final_passes(Xd, gold)
