@@ -128,8 +128,8 @@ typedef struct bm_stats {
   int64_t lloyd_iters;    /* assignment passes over samples inside K-means        */
   int64_t reseeded;       /* centroids placed by K-means++                        */
   int64_t n_d;            /* distance evaluations at sample level (Sec. 5's n_d)  */
-  int64_t boundary_draws; /* D^2 draws that fell within 1e-12 W of a boundary of  */
-                          /* the running sum (rounding-order sensitive)           */
+  int64_t boundary_draws; /* D^2 draws that fell within rounding of a boundary of */
+                          /* the running sum, retaken with row-order sums         */
   double f_opt;           /* objective of the incumbent on its own sample         */
   double ms_solver;       /* device time of the sample loop                       */
   double ms_final;        /* device time of the final assignment pass             */

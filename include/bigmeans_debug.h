@@ -35,6 +35,13 @@ int32_t bm_debug_mfma_lloyd(int32_t on);
  * the previous setting, or -1 for another value.  Process-wide. */
 int32_t bm_debug_fp32_mfma(int32_t on);
 
+/* K-means++ D^2 draws (Sec. 2): 1 takes every draw with W and the running
+ * sum added one row at a time in row order, 0 (default) only the draws that
+ * the chunked sums leave within rounding of a row boundary (the others pick
+ * the same row either way); each such draw adds one to boundary_draws.
+ * Returns the previous setting, or -1 for another value.  Process-wide. */
+int32_t bm_debug_exact_draws(int32_t on);
+
 /* Copies the first n raw device counters of this thread's last bigmeans_fit
  * (passes, reseeds, replacements, n_d, boundary draws, samples, sampler
  * passes, then per-phase clock ticks) into out.  BM_EINVAL for out NULL or

@@ -588,6 +588,15 @@ def debug_fp32_mfma(on):
     return L.bm_debug_fp32_mfma(on)
 
 
+def debug_exact_draws(on):
+    """K-means++ draws: 1 = every draw with row-order sums, 0 = only the draws
+    near a running-sum boundary (default); returns the previous value."""
+    L = load()
+    L.bm_debug_exact_draws.argtypes = [ct.c_int32]
+    L.bm_debug_exact_draws.restype = ct.c_int32
+    return L.bm_debug_exact_draws(on)
+
+
 def debug_mfma_lloyd(on):
     """BF16 matrix-core fits: 1 = sample-level K-means on the matrix cores
     (default), 0 = on the FP32 persistent solver; returns the previous value."""

@@ -27,6 +27,10 @@ static std::atomic<int> g_presample_mode{0};
 static std::atomic<int> g_mfma_lloyd{1};
 static std::atomic<int> g_fp32_mfma{1};
 bool fp32_mfma_enabled() { return g_fp32_mfma.load() != 0; }
+// 1: every K-means++ draw is taken with the row-order sums, not only those
+// near a boundary (a test hook).
+static std::atomic<int> g_exact_draws{0};
+bool exact_draws_forced() { return g_exact_draws.load() != 0; }
 static thread_local int64_t g_last_rechecked = 0;
 static thread_local double g_last_assign_ms = 0.0;
 static thread_local int32_t g_last_batch_rounds = 0;
@@ -646,6 +650,13 @@ int32_t bm_debug_fp32_mfma(int32_t on) {
   return g_fp32_mfma.exchange(on);
 }
 
+// Test hook: every K-means++ draw with the row-order sums (1) or only the
+// draws near a running-sum boundary (0); returns the previous setting.
+int32_t bm_debug_exact_draws(int32_t on) {
+  if (on != 0 && on != 1) return -1;
+  return g_exact_draws.exchange(on);
+}
+
 // Raw per-phase counters of the last bigmeans_fit on this thread.
 int32_t bm_debug_counters(int64_t* out, int32_t n) {
   if (!out || n < 1) return BM_EINVAL;
@@ -1072,6 +1083,7 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
     stats->lloyd_iters = passes_total;
     stats->reseeded = reseeded;
     stats->n_d = nd;
+    stats->boundary_draws = seed_counters[kCntBoundary];
     stats->f_opt = f_opt;
     stats->ms_solver = elapsed_ms(ev[0], ev[1]);
     stats->ms_final = final_pass ? elapsed_ms(ev[1], ev[2]) : 0.0;
@@ -1578,7 +1590,7 @@ static bm_status collective_run(const void* X, int64_t n, int32_t d, int32_t k, 
   std::vector<int32_t> k_arr(W, k), passes(W);
   std::vector<double> fw(W);
   double f_opt = __builtin_inf();
-  int64_t replaced = 0, lloyd_iters = 0, reseeded = 0, seed_nd = 0;
+  int64_t replaced = 0, lloyd_iters = 0, reseeded = 0, boundary = 0;
   float* const Pb = b.a.P;
   // the incumbent lives in the caller's buffer: all degenerate (NaN) at first
   BM_HIP(hipMemsetAsync(centroids, 0xFF, cbytes, stream));
@@ -1648,7 +1660,7 @@ static bm_status collective_run(const void* X, int64_t n, int32_t d, int32_t k, 
         BM_HIP(hipMemcpyAsync(cnt, q.counters, sizeof cnt, hipMemcpyDeviceToHost, stream));
         if ((st = check_solver_error(q, stream, nullptr)) != BM_OK) return st;
         reseeded += cnt[kCntReseeded];
-        seed_nd += cnt[kCntND];
+        boundary += cnt[kCntBoundary];
       }
       BM_HIP(hipMemcpyAsync(degw.data(), Dw, degw.size(), hipMemcpyDeviceToHost, stream));
       BM_HIP(hipStreamSynchronize(stream));
@@ -1702,6 +1714,7 @@ static bm_status collective_run(const void* X, int64_t n, int32_t d, int32_t k, 
     stats->lloyd_iters = lloyd_iters;
     stats->reseeded = reseeded;
     stats->n_d = -1;  // the batched kernels do not count distance evaluations
+    stats->boundary_draws = boundary;
     stats->f_opt = f_opt;
   }
   return BM_OK;

@@ -85,6 +85,7 @@ struct SolverArgs {
   uint64_t win_lo;           // predicted key window of the sampler (inclusive)
   uint64_t win_hi;
   uint32_t spin_limit;
+  int32_t exact_draws;       // 1: every K-means++ draw takes the row-order sums (a test hook)
   int32_t sbatch;            // samples drawn per batch (slots of the buffers below)
   int32_t presampled;        // 1: every sample was drawn before the solver launch
   int32_t* presample_miss;   // 1: a presampled window missed (the solver samples)
@@ -242,6 +243,7 @@ bm_status launch_assign_mfma32(const float* X, int64_t n, int d, const float* C,
                                double* sse_dev, unsigned long long* rechecked, int grid,
                                hipStream_t stream);
 bool fp32_mfma_enabled();
+bool exact_draws_forced();  // every K-means++ draw takes the row-order sums (test hook)
 // The batched assignment with matrix-core labels (same results as
 // launch_batch_assign's kernel; no labels_in / partial-block modes).
 size_t batch_assign_mfma32_lds(int d, int kmax, bool sums_lds);

@@ -764,6 +764,59 @@ __device__ __forceinline__ double min_dist2_f64_stream(const float* __restrict__
   return best;
 }
 
+constexpr int kLocRows = 4;
+
+// A D^2 draw within this distance of a row boundary may fall on the other
+// side of it when W and the running sum are added one row at a time in row
+// order: for nonnegative terms, any order of summation is within about
+// s units of rounding of W of the exact sums, the two targets u W differ by
+// as much again, and the row-order sums likewise (4 s plus a margin).
+__device__ __forceinline__ double draw_tol(int64_t s, double W) {
+  return (4.0 * static_cast<double>(s) + 64.0) * 0x1p-53 * W;
+}
+
+// Lane j's double, read into every lane (j uniform).
+__device__ __forceinline__ double lane_f64(double v, int j) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b), j));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), j));
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// The D^2 draw of K-means++ (Sec. 2) with W and the running sum added one row
+// at a time in row order: the first row whose running sum exceeds unit * W;
+// when rounding leaves none, the last row with weight; -1 when every weight is
+// zero.  Run by one whole wavefront (every lane gets the result): rows are
+// loaded 64 at a time and added lane by lane.  Used for the rare draws that
+// the chunked sums leave within draw_tol of a boundary.
+__device__ int64_t seq_draw(const double* __restrict__ w, int64_t s, double unit) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double W = 0.0;
+  for (int64_t b = 0; b < s; b += kWave) {
+    const double v = (b + lane < s) ? w[b + lane] : 0.0;  // zeros past s add nothing
+#pragma unroll 8
+    for (int j = 0; j < kWave; ++j) W += lane_f64(v, j);
+  }
+  const double target = unit * W;
+  double run = 0.0;
+  for (int64_t b = 0; b < s; b += kWave) {
+    const double v = (b + lane < s) ? w[b + lane] : 0.0;
+    int hit = -1;
+#pragma unroll 8
+    for (int j = 0; j < kWave; ++j) {
+      run += lane_f64(v, j);
+      if (hit < 0 && run > target) hit = j;
+    }
+    if (hit >= 0) return b + hit;  // a padding zero never first exceeds the target
+  }
+  for (int64_t b = ((s - 1) / kWave) * kWave; b >= 0; b -= kWave) {
+    const double v = (b + lane < s) ? w[b + lane] : 0.0;
+    const unsigned long long m = __ballot(v > 0.0);
+    if (m) return b + 63 - __builtin_clzll(m);
+  }
+  return -1;
+}
+
 // The row of chunk [o0, o1) whose running weight sum (from `base`, rows in
 // index order) first exceeds `target`; every workgroup calls it with the same
 // arguments and gets the same row.  Thread tid holds the weights of its run of
@@ -771,8 +824,7 @@ __device__ __forceinline__ double min_dist2_f64_stream(const float* __restrict__
 // block-wide scan orders the runs, and the thread whose run holds the target
 // walks it.  A target beyond the chunk's total (rounding) takes the chunk's
 // last row with weight.  Returns the row and sets *near when the target lies
-// within 1e-12 W of the row's boundaries.  Longer runs are read from memory.
-constexpr int kLocRows = 4;
+// within tol of the row's boundaries.  Longer runs are read from memory.
 __device__ __forceinline__ void chunk_run(int64_t o0, int64_t o1, int64_t* i0, int* nr) {
   const int64_t rpt = (o1 - o0 + kBlock - 1) / kBlock;
   const int64_t a = o0 + threadIdx.x * rpt < o1 ? o0 + threadIdx.x * rpt : o1;
@@ -795,7 +847,7 @@ __device__ __forceinline__ void load_run(const double* __restrict__ w, int64_t o
 template <bool REG>
 __device__ __forceinline__ int64_t locate_in_chunk(const double (&wv)[kLocRows], const double* __restrict__ w,
                                                    int64_t o0, int64_t o1, double base, double target,
-                                                   double W, Lds& L, bool* near) {
+                                                   double tol, Lds& L, bool* near) {
   const int tid = threadIdx.x;
   int64_t i0;
   int nr;
@@ -835,7 +887,7 @@ __device__ __forceinline__ int64_t locate_in_chunk(const double (&wv)[kLocRows],
         run += wt(q);
         if (run > target) {
           pick = i0 + q;
-          nb = ((run - target) < 1e-12 * W || (target - prev) < 1e-12 * W) ? 1 : 0;
+          nb = ((run - target) < tol || (target - prev) < tol) ? 1 : 0;
           found = true;
         }
       }
@@ -888,11 +940,11 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
     }
   };
   auto get_w = [&](int64_t tile, int64_t i) { return cached ? w_reg : a.w[i]; };
-  // LEAN: the weights also go to a.w in cached mode (every workgroup reads
-  // the chunk that holds a draw's target)
+  // the weights also go to a.w in cached mode: a draw's target may lie in
+  // another workgroup's chunk, and a draw near a boundary reads them all
   auto set_w = [&](int64_t i, double v) {
     if (cached) w_reg = v;
-    if (LEAN || !cached) a.w[i] = v;
+    a.w[i] = v;
   };
 
   // phase ticks of workgroup 0, kept in registers and added to the counters
@@ -1007,11 +1059,20 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
           }
           chunk_of(l, &o0, &o1);
           bool near = false;
-          const int64_t c = reg ? locate_in_chunk<true>(wv, a.w, o0, o1, basev[l], tgt[l], W, L, &near)
-                                : locate_in_chunk<false>(wv, a.w, o0, o1, basev[l], tgt[l], W, L, &near);
-          if (tid == 0) cand_l[l] = c;
-          if (near && g == 0 && tid == 0)
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntBoundary]), 1ull);
+          const double tol = draw_tol(s, W);
+          const int64_t c = reg ? locate_in_chunk<true>(wv, a.w, o0, o1, basev[l], tgt[l], tol, L, &near)
+                                : locate_in_chunk<false>(wv, a.w, o0, o1, basev[l], tgt[l], tol, L, &near);
+          if (near || a.exact_draws) {
+            // near a boundary: the draw as the row-order sums take it
+            if (tid < kWave) {
+              const int64_t r = seq_draw(a.w, s, unit_from_word(seed_draw(a.seed, t, q - trials + l)));
+              if (tid == 0) cand_l[l] = r;
+            }
+            if (g == 0 && tid == 0)
+              atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntBoundary]), 1ull);
+          } else if (tid == 0) {
+            cand_l[l] = c;
+          }
 #pragma unroll
           for (int q = 0; q < kLocRows; ++q) wv[q] = wn[q];
         }
@@ -1030,6 +1091,7 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
         for (int l = 0; l < trials; ++l) {
           if (owner[l] != g) continue;
           const double target = tgt[l];
+          const double tol = draw_tol(s, W);
           double run = basev[l];
           if (tid == 0) { L.misc64[1] = -1; L.misc64[3] = 0; }
           __syncthreads();
@@ -1050,7 +1112,7 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
               if (tid == first) {
                 L.misc64[1] = i;
                 const double prev = v - wi;
-                L.misc64[3] = ((v - target) < 1e-12 * W || (target - prev) < 1e-12 * W) ? 1 : 0;
+                L.misc64[3] = ((v - target) < tol || (target - prev) < tol) ? 1 : 0;
               }
               __syncthreads();
               break;
@@ -1073,9 +1135,17 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
             }
             __syncthreads();
           }
+          if (L.misc64[3] || a.exact_draws) {
+            // near a boundary: the draw as the row-order sums take it
+            if (tid < kWave) {
+              const int64_t r = seq_draw(a.w, s, unit_from_word(seed_draw(a.seed, t, q - trials + l)));
+              if (tid == 0) L.misc64[1] = r;
+            }
+            if (tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntBoundary]), 1ull);
+            __syncthreads();
+          }
           if (tid == 0) {
             a.cand[l] = L.misc64[1];
-            if (L.misc64[3]) atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[kCntBoundary]), 1ull);
             if (L.misc64[1] < 0) set_err(a, kErrSeed);
           }
           __syncthreads();
@@ -1927,6 +1997,7 @@ bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t s
       return set_error(BM_ENOTSUP, "cannot reserve %zu B of LDS: %s", lds, hipGetErrorString(ea));
   }
   SolverArgs copy = a;
+  copy.exact_draws = exact_draws_forced() ? 1 : 0;
   void* args[] = {&copy};
   const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlock), args,
                                                   static_cast<unsigned int>(lds), stream);
