@@ -66,6 +66,12 @@ struct Slot {
 // --- BM_SERVE_ROUNDS ------------------------------------------------------
 
 constexpr int kRoundTile = 512;  // sample rows per work-list tile
+// Rounds queued per host synchronisation of the round thread.  A solve that
+// finishes inside the group is skipped by the rest of it (the batched kernels
+// skip done solves), so its results are those of a round-by-round loop; it
+// waits at most kRoundsPerSync - 1 rounds longer for its hand-over, while
+// every other job saves kRoundsPerSync - 1 synchronisations and hand-overs.
+constexpr int kRoundsPerSync = 4;
 
 // Jobs whose Lloyd rounds run in the same launch: same d and stop rule.
 struct ClassKey {
@@ -683,13 +689,15 @@ void bm_ctx::engine() {
         failed.push_back(r);
       }
     }
-    // one round per class with running solves
+    // kRoundsPerSync rounds per class with running solves
     bm_status rst = BM_OK;
-    for (auto& kv : arenas) {
-      Arena& A = *kv.second;
-      if (A.in_lloyd == 0) continue;
-      clear_error();
-      if ((rst = arena_round(A, stream)) != BM_OK) break;
+    for (int rr = 0; rr < kRoundsPerSync && rst == BM_OK; ++rr) {
+      for (auto& kv : arenas) {
+        Arena& A = *kv.second;
+        if (A.in_lloyd == 0) continue;
+        clear_error();
+        if ((rst = arena_round(A, stream)) != BM_OK) break;
+      }
     }
     if (rst == BM_OK && hipStreamSynchronize(stream) != hipSuccess)
       rst = set_error(BM_EDEVICE, "a batched round failed");

@@ -219,3 +219,28 @@ def test_batched_wide_workload_sampled():
             olab, _, of = oracle.assign(Pn, Cb, dgj)
         assert_sse(f[j], of)
         assert_labels(lab[r0[j]:r0[j + 1]].cpu().numpy(), olab, Pn, Cb, dgj)
+
+
+@pytest.mark.parametrize("d,k", [(4, 6), (24, 16)])
+def test_batched_nonfinite_rows_stay_in_their_problem(d, k):
+    # a NaN row and an infinite row in problem 0 go to its first active slot
+    # (as in the persistent solver) and touch nothing outside problem 0: the
+    # other problems come out bit for bit as in a batch without those rows
+    # (k d = 24 runs the VALU kernel, k d = 384 the matrix-core one)
+    clean = _problems([(3_000, k), (2_500, k), (1_800, k)], d, seed=41)
+    bad = [(p.copy(), c.copy(), g.copy()) for p, c, g in clean]
+    bad[0][0][7, 1] = np.nan
+    bad[0][0][11, 0] = np.inf
+    print(f"batched nonfinite rows d={d} k={k}", flush=True)
+    got, _ = _run_batched(bad, max_iter=30, stop_rule=1)
+    ref, _ = _run_batched(clean, max_iter=30, stop_rule=1)
+    for j in (1, 2):
+        gC, gdeg, glab, gf, gp = got[j]
+        rC, rdeg, rlab, rf, rp = ref[j]
+        np.testing.assert_array_equal(gC, rC)
+        np.testing.assert_array_equal(gdeg, rdeg)
+        np.testing.assert_array_equal(glab, rlab)
+        assert gf == rf and gp == rp
+    glab0 = got[0][2]
+    first_active = int(np.flatnonzero(bad[0][2] == 0)[0])
+    assert glab0[7] == first_active and glab0[11] == first_active
