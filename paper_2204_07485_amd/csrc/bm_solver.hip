@@ -766,6 +766,20 @@ __device__ __forceinline__ double min_dist2_f64_stream(const float* __restrict__
 
 constexpr int kLocRows = 4;
 
+// Workgroup minimum (maximum) of `value` over the threads whose `pred` holds,
+// for values that increase with the thread index: in each wavefront the
+// lowest (highest) such lane holds the wavefront's extreme and alone updates
+// *dst (LDS), so the word takes one atomic per wavefront instead of one per
+// thread.  Called by every lane of the wavefront.
+__device__ __forceinline__ void wave_min_first(bool pred, int value, int* dst) {
+  const unsigned long long m = __ballot(pred);
+  if (m && static_cast<int>(threadIdx.x & (kWave - 1)) == __builtin_ctzll(m)) atomicMin(dst, value);
+}
+__device__ __forceinline__ void wave_max_last(bool pred, int value, int* dst) {
+  const unsigned long long m = __ballot(pred);
+  if (m && static_cast<int>(threadIdx.x & (kWave - 1)) == 63 - __builtin_clzll(m)) atomicMax(dst, value);
+}
+
 // A D^2 draw within this distance of a row boundary may fall on the other
 // side of it when W and the running sum are added one row at a time in row
 // order: for nonnegative terms, any order of summation is within about
@@ -868,12 +882,13 @@ __device__ __forceinline__ int64_t locate_in_chunk(const double (&wv)[kLocRows],
   }
   __syncthreads();
   const double v0 = base + (tid > 0 ? incl_l[tid - 1] : 0.0);
-  if (nr > 0 && v0 + local > target) atomicMin(&L.misc[2], tid);
+  wave_min_first(nr > 0 && v0 + local > target, tid, &L.misc[2]);
   int last = -1;  // last row with weight, for a target beyond the chunk's sum
 #pragma unroll
   for (int q = 0; q < nq; ++q)
     if (q < nr && wt(q) > 0.0) last = q;
-  if (last >= 0) atomicMax(&L.misc[6], static_cast<int>(i0 - o0) + last);
+  // runs start at increasing rows, so the last weighted row is the highest lane's
+  wave_max_last(last >= 0, static_cast<int>(i0 - o0) + last, &L.misc[6]);
   __syncthreads();
   if (tid == L.misc[2]) {
     double run = v0;
@@ -1009,10 +1024,14 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
         const double e1 = e0 + w0;
         for (int l = 0; l < trials; ++l) {
           const double target = unit_from_word(seed_draw(a.seed, t, q + l)) * tot;
-          if (g0 < G && e0 + w0 > target) atomicMin(&owner[l], g0);
-          else if (g0 + 1 < G && e1 + w1 > target) atomicMin(&owner[l], g0 + 1);
-          if (g0 < G && w0 > 0.0) atomicMax(&L.tmpi[24 + l], g0);      // last chunk with weight
-          if (g0 + 1 < G && w1 > 0.0) atomicMax(&L.tmpi[24 + l], g0 + 1);
+          // first chunk whose end passes the target, and the last chunk with
+          // weight (thread tid holds chunks 2 tid and 2 tid + 1)
+          const bool h0 = g0 < G && e0 + w0 > target;
+          const bool h1 = g0 + 1 < G && e1 + w1 > target;
+          wave_min_first(h0 || h1, h0 ? g0 : g0 + 1, &owner[l]);
+          const bool p1 = g0 + 1 < G && w1 > 0.0;
+          const bool p0 = g0 < G && w0 > 0.0;
+          wave_max_last(p0 || p1, p1 ? g0 + 1 : g0, &L.tmpi[24 + l]);
           if (tid == 0) tgt[l] = target;
         }
         __syncthreads();
@@ -1105,7 +1124,7 @@ __device__ __forceinline__ bool reseed_phase(const SolverArgs& a, Lds& L, uint32
             // first hitting row of the tile: minimum over hitting threads
             if (tid == 0) L.misc[2] = 0x7fffffff;
             __syncthreads();
-            if (hit) atomicMin(&L.misc[2], tid);
+            wave_min_first(hit, tid, &L.misc[2]);
             __syncthreads();
             const int first = L.misc[2];
             if (first != 0x7fffffff) {
