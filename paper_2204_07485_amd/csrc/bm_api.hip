@@ -206,7 +206,7 @@ struct SolverPlan {
   int gmax = 0;  // co-resident workgroups of this configuration on the device
   int64_t cand_cap = 0;
   uint64_t win_lo = 0, win_hi = 0;
-  bool sums_in_lds = false;
+  int sums_in_lds = 0;  // replicas of the FP64 sums in LDS (0: global ring)
   bool c64_in_lds = false;
   size_t lds = 0;
 };
@@ -219,10 +219,13 @@ static bm_status plan_solver(int d, int k, int64_t s, int64_t n_points, int grid
   bm_status st = max_lds_per_block(&lds_max);
   if (st != BM_OK) return st;
   const size_t budget = lds_max > 2048 ? lds_max - 2048 : lds_max;  // static LDS of the kernel
-  // prefer, in order: FP64 sums in LDS, FP64 means in LDS
+  // prefer, in order: FP64 sums (4, then 2 replicas) and means in LDS, then
+  // FP64 sums in LDS, then FP64 means in LDS
   bool found = false;
-  for (int mode = 3; mode >= 0 && !found; --mode) {
-    const bool sl = (mode & 2) != 0, cl = (mode & 1) != 0;
+  const int modes[6][2] = {{4, 1}, {2, 1}, {1, 1}, {1, 0}, {0, 1}, {0, 0}};
+  for (int mi = 0; mi < 6 && !found; ++mi) {
+    const int sl = modes[mi][0];
+    const bool cl = modes[mi][1] != 0;
     const size_t need = solver_lds_bytes(sp->dm, k, d, sl, cl);
     if (need <= budget) {
       sp->sums_in_lds = sl;

@@ -79,7 +79,7 @@ struct SolverArgs {
   uint64_t budget_ticks;     // > 0: stop before a sample once this many wall-clock
                              // ticks have passed since the launch (sample 0 always runs)
   int32_t* stop_flag;        // workgroup 0's budget decision, read after a grid barrier
-  int32_t sums_in_lds;
+  int32_t sums_in_lds;       // replicas (1, 2, 4) of the FP64 cluster sums in LDS; 0: global ring
   int32_t c64_in_lds;
   int64_t cand_cap;          // capacity of the global candidate list
   uint64_t win_lo;           // predicted key window of the sampler (inclusive)
@@ -158,7 +158,7 @@ bm_status set_error(bm_status code, const char* fmt, ...);
 void clear_error();
 
 // Launchers (defined in bm_solver.hip / bm_assign.hip).
-size_t solver_lds_bytes(int dm, int k, int d, bool sums_in_lds, bool c64_in_lds);
+size_t solver_lds_bytes(int dm, int k, int d, int sums_reps, bool c64_in_lds);
 void sampler_window(int64_t n, int64_t s, uint64_t* lo, uint64_t* hi, int64_t* cap);
 // Samples drawn per batch by bigmeans_fit: all T when their buffers (rows,
 // indices, codes, candidates) fit in kSampleBatchBytes, else fewer (>= 1).

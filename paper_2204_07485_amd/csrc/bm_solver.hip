@@ -51,6 +51,13 @@ __device__ __forceinline__ int64_t imin64(int64_t x, int64_t y) { return x < y ?
 // coordinate of different clusters falls in different LDS banks.
 __host__ __device__ __forceinline__ int sums_ld(int d) { return (d & 1) ? d : d + 1; }
 
+// The LDS sums come in `reps` replicas (1, 2 or 4): lane l of a wavefront adds
+// into replica l % reps, so lanes of one wavefront with the same label hit
+// reps different words (same-address LDS atomics are serialised), and the
+// replicas are added in a fixed order when the workgroup flushes.  Replica
+// stride in doubles: odd, so a word's replicas fall in different banks.
+__host__ __device__ __forceinline__ int sums_rstride(int k, int d) { return (k * sums_ld(d)) | 1; }
+
 __host__ __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 struct LdsPlan {
@@ -60,7 +67,9 @@ struct LdsPlan {
   size_t total;
 };
 
-__host__ __device__ inline LdsPlan plan_lds(int dm, int k, int d, bool sums_in_lds,
+// sums_reps: replicas of the FP64 cluster sums in LDS (0: the sums are
+// accumulated in the global ring instead).
+__host__ __device__ inline LdsPlan plan_lds(int dm, int k, int d, int sums_reps,
                                             bool c64_in_lds) {
   LdsPlan p;
   size_t o = 0;
@@ -84,8 +93,8 @@ __host__ __device__ inline LdsPlan plan_lds(int dm, int k, int d, bool sums_in_l
   if (b < seed_stage) b = seed_stage;
   p.total_sampling = b;
   b = 0;
-  p.sums = b; b = align16(b + (sums_in_lds ? sizeof(double) * size_t(k) * sums_ld(d) : 0));
-  p.cntl = b; b = align16(b + sizeof(int) * size_t(k));
+  p.sums = b; b = align16(b + (sums_reps ? sizeof(double) * size_t(sums_reps) * sums_rstride(k, d) : 0));
+  p.cntl = b; b = align16(b + sizeof(int) * size_t(k) * (sums_reps > 1 ? sums_reps : 1));
   p.total_lloyd = b;
   p.total = o + (p.total_sampling > p.total_lloyd ? p.total_sampling : p.total_lloyd);
   return p;
@@ -1364,10 +1373,14 @@ __device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& 
     for (int j = tid; j < kReplicas * k; j += kBlock) ncring[j] = 0;
   }
   const int ld = a.sums_in_lds ? sums_ld(d) : d;
+  const int reps = a.sums_in_lds > 1 ? a.sums_in_lds : 1;  // LDS replicas
+  const int rstride = sums_rstride(k, d);
+  const int rep_l = tid & (reps - 1);                        // this lane's replica
+  int* cnt_rep = cnt_l + rep_l * k;
   if (accumulate) {
     if (a.sums_in_lds)
-      for (int e = tid; e < k * ld; e += kBlock) sums_l[e] = 0.0;
-    for (int j = tid; j < k; j += kBlock) cnt_l[j] = 0;
+      for (int e = tid; e < reps * rstride; e += kBlock) sums_l[e] = 0.0;
+    for (int j = tid; j < reps * k; j += kBlock) cnt_l[j] = 0;
     __syncthreads();
   }
   const uint64_t a1 = wall_clock64();
@@ -1378,31 +1391,42 @@ __device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& 
 #pragma unroll
       for (int q = 0; q < RowCache<DM>::kRows; ++q) {
         const int64_t i = r0 + tid + static_cast<int64_t>(q) * kBlock;
-        if (i < r1) assign_row<DM, kL>(a, L, rc.x[q], i, na, accumulate, sums_dst, ld, cnt_l, sse);
+        if (i < r1) assign_row<DM, kL>(a, L, rc.x[q], i, na, accumulate, sums_dst, ld, cnt_rep, sse);
       }
     } else {
       for (int64_t i = r0 + tid; i < r1; i += kBlock) {
         float x[DM];
         load_row_f32<DM>(a.P + static_cast<size_t>(i) * d, d, x);
-        assign_row<DM, kL>(a, L, x, i, na, accumulate, sums_dst, ld, cnt_l, sse);
+        assign_row<DM, kL>(a, L, x, i, na, accumulate, sums_dst, ld, cnt_rep, sse);
       }
     }
   };
-  if (a.sums_in_lds) rows(std::true_type{}, sums_l);
+  if (a.sums_in_lds) rows(std::true_type{}, sums_l + static_cast<size_t>(rep_l) * rstride);
   else rows(std::false_type{}, ring);
   __syncthreads();
   const uint64_t a2 = wall_clock64();
   const double wsse = block_sum_f64<kBlock>(sse, L.tmpd);
   const uint64_t f0 = wall_clock64();
   if (accumulate) {
+    auto count = [&](int j) {
+      int c = 0;
+      for (int r = 0; r < reps; ++r) c += cnt_l[r * k + j];
+      return c;
+    };
     if (a.sums_in_lds) {
       for (int e = tid; e < kd; e += kBlock) {
         const int j = e / d;
-        if (cnt_l[j]) unsafeAtomicAdd(&ring[e], sums_l[j * ld + (e - j * d)]);
+        if (!count(j)) continue;
+        const int q = j * ld + (e - j * d);
+        double v = sums_l[q];
+        for (int r = 1; r < reps; ++r) v += sums_l[r * rstride + q];  // fixed order
+        unsafeAtomicAdd(&ring[e], v);
       }
     }
-    for (int j = tid; j < k; j += kBlock)
-      if (cnt_l[j]) atomicAdd(&cring[j], cnt_l[j]);
+    for (int j = tid; j < k; j += kBlock) {
+      const int c = count(j);
+      if (c) atomicAdd(&cring[j], c);
+    }
   }
   if (tid == 0) a.sse_part[(pass & 1u) * kMaxGrid + g] = wsse;
   const uint64_t b0 = wall_clock64();
@@ -1656,7 +1680,7 @@ __device__ __forceinline__ void store_incumbent(const SolverArgs& a, Lds& L, dou
 template <int DM>
 __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds != 0, a.c64_in_lds != 0);
+  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds, a.c64_in_lds != 0);
   Lds L = carve(lds_raw, pl);
   const int tid = threadIdx.x;
   const int g = blockIdx.x;
@@ -1798,7 +1822,7 @@ __global__ void __launch_bounds__(kBlock) solver_kernel(SolverArgs a) {
 template <int DM>
 __global__ void __launch_bounds__(kBlock) seed_kernel(SolverArgs a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds != 0, a.c64_in_lds != 0);
+  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds, a.c64_in_lds != 0);
   Lds L = carve(lds_raw, pl);
   const int tid = threadIdx.x;
   const int g = blockIdx.x;
@@ -1845,7 +1869,7 @@ __global__ void __launch_bounds__(kBlock) seed_kernel(SolverArgs a) {
 template <int DM>
 __global__ void __launch_bounds__(kBlock) presample_collect_kernel(SolverArgs a, int gp) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds != 0, a.c64_in_lds != 0);
+  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds, a.c64_in_lds != 0);
   Lds L = carve(lds_raw, pl);
   const int g = blockIdx.x, b = blockIdx.y;
   const int64_t npairs = (a.n + 1) >> 1;
@@ -1859,7 +1883,7 @@ __global__ void __launch_bounds__(kBlock) presample_collect_kernel(SolverArgs a,
 template <int DM>
 __global__ void __launch_bounds__(kBlock) presample_select_kernel(SolverArgs a, int gp) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds != 0, a.c64_in_lds != 0);
+  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds, a.c64_in_lds != 0);
   Lds L = carve(lds_raw, pl);
   const int b = blockIdx.x;
   const int64_t npairs = (a.n + 1) >> 1;
@@ -1881,7 +1905,7 @@ template <int DM>
 __global__ void __launch_bounds__(kBlock) presample_emit_kernel(SolverArgs a, int gp) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   if (__hip_atomic_load(a.presample_miss, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds != 0, a.c64_in_lds != 0);
+  const LdsPlan pl = plan_lds(DM, a.k, a.d, a.sums_in_lds, a.c64_in_lds != 0);
   Lds L = carve(lds_raw, pl);
   const int g = blockIdx.x, b = blockIdx.y;
   const int64_t npairs = (a.n + 1) >> 1;
@@ -1933,8 +1957,8 @@ int padded_dim(int d) {
   return -1;
 }
 
-size_t solver_lds_bytes(int dm, int k, int d, bool sums_in_lds, bool c64_in_lds) {
-  return plan_lds(dm, k, d, sums_in_lds, c64_in_lds).total;
+size_t solver_lds_bytes(int dm, int k, int d, int sums_reps, bool c64_in_lds) {
+  return plan_lds(dm, k, d, sums_reps, c64_in_lds).total;
 }
 
 static const void* seed_fn(int dm) {
