@@ -535,9 +535,9 @@ static bm_status batched_run(int32_t n_solves, const float* P, int32_t d, const 
   } else if (rows < 65536) {
     tile_rows = 512;
   } else {
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    BM_HIPB(hipEventCreate(&t0));
-    BM_HIPB(hipEventCreate(&t1));
+    EventSet<2> tev;
+    BM_HIPB(tev.create());
+    hipEvent_t t0 = tev[0], t1 = tev[1];
     float best = 0.f;
     for (int tr : {256, 512, 1024, 2048, 4096}) {
       bm_status su = upload(tr);
@@ -558,8 +558,6 @@ static bm_status batched_run(int32_t n_solves, const float* P, int32_t d, const 
         tile_rows = tr;
       }
     }
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
     g_tile_cache[shape] = tile_rows;
   }
   if ((st = upload(tile_rows)) != BM_OK) return fail(st);
@@ -579,9 +577,9 @@ static bm_status batched_run(int32_t n_solves, const float* P, int32_t d, const 
   BM_HIPB(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   int still = 1;
   int rounds = 0;
-  hipEvent_t r0 = nullptr, r1 = nullptr;
-  BM_HIPB(hipEventCreate(&r0));
-  BM_HIPB(hipEventCreate(&r1));
+  EventSet<2> rev;
+  BM_HIPB(rev.create());
+  hipEvent_t r0 = rev[0], r1 = rev[1];
   g_last_batch_ms.clear();
   for (; rounds <= o.max_iter && still; ++rounds) {
     BM_HIPB(hipMemsetAsync(running, 0, sizeof(int), stream));
@@ -592,8 +590,6 @@ static bm_status batched_run(int32_t n_solves, const float* P, int32_t d, const 
     BM_HIPB(hipStreamSynchronize(stream));
     g_last_batch_ms.push_back(elapsed_ms(r0, r1));
   }
-  (void)hipEventDestroy(r0);
-  (void)hipEventDestroy(r1);
   if (still) return fail(set_error(BM_EDEVICE, "batched Lloyd did not finish in max_iter + 1 rounds"));
   BM_HIPB(hipMemcpyAsync(hs.data(), sv_d, sizeof(BatchSolve) * n_solves, hipMemcpyDeviceToHost, stream));
   BM_HIPB(hipMemcpyAsync(deg, deg_d, static_cast<size_t>(ktot), hipMemcpyDeviceToHost, stream));
@@ -866,15 +862,8 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
   if ((st = prepare_solver(stream, n, s, d, k, T, sp.cand_cap, true, true, true, true, mx_grid, T,
                            &b)) != BM_OK)
     return st;
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-  struct EvGuard {
-    hipEvent_t* e;
-    ~EvGuard() {
-      for (int i = 0; i < 3; ++i)
-        if (e[i]) (void)hipEventDestroy(e[i]);
-    }
-  } evg{ev};
-  for (auto& e : ev) BM_HIP(hipEventCreate(&e));
+  EventSet<3> ev;
+  BM_HIP(ev.create());
   BM_HIP(hipEventRecord(ev[0], stream));
 
   // (1) every sample's indices; FP32 rows too when the accumulation reads them
@@ -939,9 +928,8 @@ static bm_status fit_mfma_run(const void* X, int64_t n, int32_t d, int32_t k, in
   int64_t replaced = 0, passes_total = 0, reseeded = 0, nd = 0;
   int64_t seed_counters[kNumCounters] = {};
   // per-sample phase boundaries on the stream: start, seeded, last round
-  hipEvent_t pe[3] = {nullptr, nullptr, nullptr};
-  EvGuard peg{pe};
-  for (auto& e : pe) BM_HIP(hipEventCreate(&e));
+  EventSet<3> pe;
+  BM_HIP(pe.create());
   BatchSolve init;
   memset(&init, 0, sizeof init);
   init.row0 = 0;
@@ -1184,18 +1172,15 @@ bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int
     BM_HIP(hipMemcpyAsync(a.f_opt, &o.f_opt_in, sizeof(double), hipMemcpyHostToDevice, stream));
   }
 
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-  for (auto& e : ev) BM_HIP(hipEventCreate(&e));
+  EventSet<3> ev;
+  BM_HIP(ev.create());
   BM_HIP(hipEventRecord(ev[0], stream));
   // every sample drawn up front by ordinary launches when they all have a slot
   const int pmode = g_presample_mode.load();
   if (pmode != 1 && !budget && a.sbatch == a.T && a.T <= 65535)
     st = launch_presample(a, sp.lds, stream, pmode == 2);
   if (st == BM_OK) st = launch_solver(a, sp.grid, sp.lds, stream);
-  if (st != BM_OK) {
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    return st;
-  }
+  if (st != BM_OK) return st;
   BM_HIP(hipEventRecord(ev[1], stream));
 
   // final assignment (Alg. 1 last step) over all of X
@@ -1233,7 +1218,6 @@ bm_status fit_run(const void* X, int64_t n, int32_t d, int32_t k, int64_t s, int
   memcpy(g_last_counters, counters, sizeof counters);
   const float ms_solver = elapsed_ms(ev[0], ev[1]);
   float ms_final = final_pass ? elapsed_ms(ev[1], ev[2]) : 0.f;
-  for (auto& e : ev) (void)hipEventDestroy(e);
   if (st != BM_OK) return st;
   if (fst != BM_OK) return fst;
   int32_t polish_passes = 0;
@@ -1338,8 +1322,8 @@ bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, con
   }
   if (deg) BM_HIP(hipMemcpyAsync(deg_p, deg, size_t(k), hipMemcpyHostToDevice, stream));
   if (mfma) BM_HIP(hipMemsetAsync(rechecked_p, 0, sizeof(unsigned long long), stream));
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  for (auto& e : ev) BM_HIP(hipEventCreate(&e));
+  EventSet<2> ev;
+  BM_HIP(ev.create());
   BM_HIP(hipEventRecord(ev[0], stream));
   if (mfma) {
     st = launch_assign_mfma(static_cast<const uint16_t*>(X), n, d, C, deg ? deg_p : nullptr, k,
@@ -1350,10 +1334,7 @@ bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, con
   }
   if (st == BM_OK && hipEventRecord(ev[1], stream) != hipSuccess)
     st = set_error(BM_EDEVICE, "hipEventRecord failed");
-  if (st != BM_OK) {
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    return st;
-  }
+  if (st != BM_OK) return st;
   double v = 0.0;
   unsigned long long nrecheck = 0;
   BM_HIP(hipMemcpyAsync(&v, sse_p, sizeof v, hipMemcpyDeviceToHost, stream));
@@ -1361,7 +1342,6 @@ bm_status kmeans_assign(const void* X, int64_t n, int32_t d, const float* C, con
     BM_HIP(hipMemcpyAsync(&nrecheck, rechecked_p, sizeof nrecheck, hipMemcpyDeviceToHost, stream));
   const hipError_t sync = hipStreamSynchronize(stream);
   g_last_assign_ms = sync == hipSuccess ? elapsed_ms(ev[0], ev[1]) : 0.0;
-  for (auto& e : ev) (void)hipEventDestroy(e);
   if (sync != hipSuccess)
     return set_error(BM_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(sync));
   g_last_rechecked = static_cast<int64_t>(nrecheck);

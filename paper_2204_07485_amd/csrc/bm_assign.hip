@@ -157,12 +157,7 @@ bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float
   if (st != BM_OK) return st;
   if (lds + 1024 > lds_max)
     return set_error(BM_ENOTSUP, "k*d = %d*%d centroids do not fit in LDS", k, d);
-  if (lds > 65536) {
-    const hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                              static_cast<int>(lds));
-    if (ea != hipSuccess)
-      return set_error(BM_EDEVICE, "assign LDS attribute: %s", hipGetErrorString(ea));
-  }
+  if (bm_status sr = reserve_lds(fn, lds)) return sr;
   void* args[] = {const_cast<void**>(&X), &n, &d, const_cast<float**>(&C),
                   const_cast<uint8_t**>(&deg_dev), &k, &labels, &min_d2, &partial};
   const hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kAssignBlock), args, lds, stream);

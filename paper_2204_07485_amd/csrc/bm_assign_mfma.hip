@@ -482,9 +482,7 @@ bm_status plan_assign_mfma(const void* X, int64_t n, int d, int k, int* grid) {
   if (lds + 1024 > lds_max)
     return set_error(BM_ENOTSUP, "k*d = %d*%d split centroids do not fit in LDS for BF16 MFMA", k, d);
   const void* fn = pick_mfma(ks, mfma_vec(X, d));
-  if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         static_cast<int>(lds)) != hipSuccess)
-    return set_error(BM_ENOTSUP, "cannot reserve %zu B of LDS", lds);
+  if (bm_status sr = reserve_lds(fn, lds)) return sr;
   int dev = 0, cus = 0, per_cu = 0;
   const bool vec = mfma_vec(X, d);
   const int block = mfma_block(ks, vec);

@@ -683,9 +683,7 @@ bm_status plan_assign_mfma32(const void* X, int64_t n, int d, int k, int* grid) 
     return set_error(BM_ENOTSUP, "k*d = %d*%d centroids do not fit in LDS for FP32 MFMA", k, d);
   const bool vec = mfma32_vec(X, d);
   const void* fn = pick_mfma32(nq, vec);
-  if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         static_cast<int>(lds)) != hipSuccess)
-    return set_error(BM_ENOTSUP, "cannot reserve %zu B of LDS", lds);
+  if (bm_status sr = reserve_lds(fn, lds)) return sr;
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -754,9 +752,7 @@ bm_status launch_batch_assign_mfma32(const float* Pp, int d, const float* C, con
   const size_t lds = batch_assign_mfma32_lds(d, kmax, sums_lds);
   if (!fn || lds == ~size_t(0)) return set_error(BM_EINVAL, "batched FP32 MFMA assignment: bad plan");
   static_assert(kBM32Block == 256, "one workgroup size for the plan below");
-  if (lds > 65536 &&
-      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
-    return set_error(BM_ENOTSUP, "cannot reserve %zu B of LDS for the batched FP32 MFMA assignment", lds);
+  if (bm_status sr = reserve_lds(fn, lds)) return sr;
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||

@@ -696,9 +696,7 @@ bm_status batch_assign_grid(int d, int kmax, bool sums_lds, int* grid) {
   const void* fn = sums_lds ? pick_batch_assign<true>(padded_dim(d)) : pick_batch_assign<false>(padded_dim(d));
   if (!fn) return set_error(BM_ENOTSUP, "d = %d exceeds the limit of 256", d);
   const size_t lds = batch_assign_lds(d, kmax, sums_lds);
-  if (lds > 65536 &&
-      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
-    return set_error(BM_ENOTSUP, "cannot reserve %zu B of LDS for the batched assignment", lds);
+  if (bm_status sr = reserve_lds(fn, lds)) return sr;
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -763,10 +761,7 @@ bm_status launch_batch_update(BatchSolve* sv, int n_solves, const double* tile_f
                               hipStream_t stream, int kmax) {
   const int dm = padded_dim(d);
   const size_t lds = sizeof(double) * static_cast<size_t>(kmax) * (d | 1);
-  if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_update_kernel),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         static_cast<int>(lds)) != hipSuccess)
-    return set_error(BM_ENOTSUP, "cannot reserve %zu B of LDS for the update", lds);
+  if (bm_status sr = reserve_lds(reinterpret_cast<const void*>(&batch_update_kernel), lds)) return sr;
   hipLaunchKernelGGL(batch_update_kernel, dim3(n_solves), dim3(kUpdBlock), lds, stream, sv, tile_f,
                      sums, cnt, C, Cpad, dm, C64, deg, d, max_iter, tol, stop_rule, running);
   const hipError_t e = hipGetLastError();
@@ -872,9 +867,7 @@ bm_status launch_labels_accum(const uint16_t* P, int64_t s, int d, int k, const 
     default: fn = accum_fn<32>(vec); break;
   }
   const size_t lds = labels_accum_lds(d, k);
-  if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         static_cast<int>(lds)) != hipSuccess)
-    return set_error(BM_ENOTSUP, "cannot reserve %zu B of LDS for the accumulation", lds);
+  if (bm_status sr = reserve_lds(fn, lds)) return sr;
   int dm = padded_dim(d);
   int c_vec = (d & 3) == 0 && (reinterpret_cast<uintptr_t>(C) & 15) == 0;
   void* args[] = {const_cast<uint16_t**>(&P), &s, &d, &dm, &k, const_cast<float**>(&C), &c_vec,

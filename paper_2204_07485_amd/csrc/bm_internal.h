@@ -171,6 +171,31 @@ bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t s
 bm_status launch_presample(SolverArgs& a, size_t lds, hipStream_t stream, bool force_miss = false);
 bm_status solver_max_grid(int dm, size_t lds, int* max_grid);
 bm_status max_lds_per_block(size_t* bytes);
+// Raises kernel fn's dynamic-LDS limit on the current device to at least
+// `bytes` (nothing to do up to 64 KiB).  The attribute is set once per
+// function, device and larger size, under a lock, not on every launch.
+bm_status reserve_lds(const void* fn, size_t bytes);
+
+// HIP events destroyed when the scope ends, on every return path.
+template <int N>
+struct EventSet {
+  hipEvent_t e[N] = {};
+  EventSet() = default;
+  EventSet(const EventSet&) = delete;
+  EventSet& operator=(const EventSet&) = delete;
+  ~EventSet() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+  hipError_t create() {
+    for (auto& x : e) {
+      const hipError_t r = hipEventCreate(&x);
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  }
+  hipEvent_t& operator[](int i) { return e[i]; }
+};
 
 bm_status launch_assign(const void* X, int x_bf16, int64_t n, int d, const float* C,
                         const uint8_t* deg_dev, int k, int32_t* labels, float* min_d2,

@@ -22,6 +22,10 @@
 
 #include <type_traits>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "bm_internal.h"
 #include "bm_rng.h"
 
@@ -1999,6 +2003,23 @@ bm_status max_lds_per_block(size_t* bytes) {
   return BM_OK;
 }
 
+bm_status reserve_lds(const void* fn, size_t bytes) {
+  if (bytes <= 65536) return BM_OK;
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> reserved;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return set_error(BM_EDEVICE, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& cur = reserved[{dev, fn}];
+  if (cur >= bytes) return BM_OK;
+  const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           static_cast<int>(bytes));
+  if (e != hipSuccess)
+    return set_error(BM_ENOTSUP, "cannot reserve %zu B of LDS: %s", bytes, hipGetErrorString(e));
+  cur = bytes;
+  return BM_OK;
+}
+
 bm_status solver_max_grid(int dm, size_t lds, int* max_grid) {
   const void* fn = solver_fn(dm);
   if (!fn) return set_error(BM_ENOTSUP, "no solver for padded dimension %d", dm);
@@ -2033,12 +2054,7 @@ bm_status launch_solver(const SolverArgs& a, int grid, size_t lds, hipStream_t s
                          a.T == 1 && !a.init_incumbent && !a.budget_ticks;
   const void* fn = seed_only ? seed_fn(dm) : solver_fn(dm);
   if (!fn) return set_error(BM_ENOTSUP, "dimension %d exceeds the solver's limit of 256", a.d);
-  if (lds > 65536) {
-    const hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                              static_cast<int>(lds));
-    if (ea != hipSuccess)
-      return set_error(BM_ENOTSUP, "cannot reserve %zu B of LDS: %s", lds, hipGetErrorString(ea));
-  }
+  if (bm_status sr = reserve_lds(fn, lds)) return sr;
   SolverArgs copy = a;
   copy.exact_draws = exact_draws_forced() ? 1 : 0;
   void* args[] = {&copy};
@@ -2074,11 +2090,8 @@ bm_status launch_presample(SolverArgs& a, size_t lds, hipStream_t stream, bool f
   int64_t gp = (npairs + 4095) / 4096;  // ~8 pairs per thread
   if (gp < 1) gp = 1;
   if (gp > kMaxGrid) gp = kMaxGrid;
-  if (lds > 65536) {
-    for (const void* f : {fc, fs, fe})
-      if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
-        return set_error(BM_ENOTSUP, "cannot reserve %zu B of LDS for presampling", lds);
-  }
+  for (const void* f : {fc, fs, fe})
+    if (bm_status sr = reserve_lds(f, lds)) return sr;
   SolverArgs copy = a;
   // wide rows are gathered by a separate coalesced pass after the emit
   const bool coop_gather = a.do_gather && a.d >= 32 && a.P && a.idx;
