@@ -280,6 +280,11 @@ bm_status kmeans_assign_noalloc(const void* X, int64_t n, int32_t d, const float
  *              ascending order; if every remaining D^2 is zero they stay 1.
  *   seed, stream_id  the draws use sample index t = stream_id (< 2^32).
  *   opt        n_local_trials (1..8) is read from here.
+ * A D^2 draw takes the first row whose running sum of weights, in row order,
+ * exceeds u W (W the sum of all weights, u the draw's uniform); the sums are
+ * formed by chunks and scans, and a draw that lands within their rounding
+ * bound of a row boundary is taken again with W and the running sum added
+ * one row at a time, so every pick is the row-order definition's.
  */
 bm_status kmeanspp_seed(const float* P, int64_t s, int32_t d, int32_t k, float* C, uint8_t* deg,
                         uint64_t seed, uint64_t stream_id, const bm_options* opt);
