@@ -1506,6 +1506,8 @@ __device__ __forceinline__ double update_centroids(const SolverArgs& a, const Ld
   // staged sums, overwritten in place by the squared coordinate moves
   double* dsq = a.sums_in_lds ? reinterpret_cast<double*>(L.B + pl.sums) : nullptr;
   const int ld = sums_ld(d);
+  // only the shift stop rule reads the largest move
+  const bool need_shift = a.stop_rule == BM_STOP_SHIFT;
   if (tid == 0) L.misc[3] = 0;
   if (dsq) {
     for (int e = tid; e < k * d; e += kBlock) {
@@ -1514,8 +1516,10 @@ __device__ __forceinline__ double update_centroids(const SolverArgs& a, const Ld
       if (L.degf[j] || c == 0) continue;
       const int q = j * ld + (e - j * d);
       const double mean = dsq[q] / static_cast<double>(c);
-      const double diff = mean - c_old[e];
-      dsq[q] = __dmul_rn(diff, diff);
+      if (need_shift) {
+        const double diff = mean - c_old[e];
+        dsq[q] = __dmul_rn(diff, diff);
+      }
       c_new[e] = mean;
       L.C[j * DM + (e - j * d)] = static_cast<float>(mean);
     }
@@ -1534,7 +1538,8 @@ __device__ __forceinline__ double update_centroids(const SolverArgs& a, const Ld
     }
     double moved = 0.0;
     if (dsq) {
-      for (int tdim = 0; tdim < d; ++tdim) moved = __dadd_rn(moved, dsq[j * ld + tdim]);
+      if (need_shift)
+        for (int tdim = 0; tdim < d; ++tdim) moved = __dadd_rn(moved, dsq[j * ld + tdim]);
     } else {
       for (int tdim = 0; tdim < d; ++tdim) {
         double sum = 0.0;
@@ -1549,6 +1554,12 @@ __device__ __forceinline__ double update_centroids(const SolverArgs& a, const Ld
     }
     moved = sqrt(moved);
     local = moved > local ? moved : local;
+  }
+  if (!need_shift) {
+    __syncthreads();
+    if (L.misc[3]) rebuild_active(L, k);  // a cluster emptied this round
+    __syncthreads();
+    return 0.0;
   }
   // block max (exact, order-free)
   const int lane = tid & (kWave - 1);
