@@ -129,19 +129,16 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* tmp, T& total) {
   }
   if (lane == kWave - 1) tmp[wave] = incl;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    T run = T(0);
-    for (int w = 0; w < NW; ++w) {
-      const T x = tmp[w];
-      tmp[w] = run;
-      run += x;
-    }
-    tmp[NW] = run;
+  // every thread runs the same in-order pass over the wavefront totals
+  T run = T(0), before = T(0);
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w == wave) before = run;
+    run += tmp[w];
   }
-  __syncthreads();
-  const T excl = incl - v + tmp[wave];
-  total = tmp[NW];
-  __syncthreads();
+  const T excl = incl - v + before;
+  total = run;
+  __syncthreads();  // tmp may be reused at once
   return excl;
 }
 
@@ -160,19 +157,16 @@ __device__ __forceinline__ double block_inclusive_scan_f64(double v, double* tmp
   }
   if (lane == kWave - 1) tmp[wave] = incl;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double run = 0.0;
-    for (int w = 0; w < NW; ++w) {
-      const double x = tmp[w];
-      tmp[w] = run;
-      run += x;
-    }
-    tmp[NW] = run;
+  // every thread runs the same in-order pass over the wavefront totals
+  double run = 0.0, before = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w == wave) before = run;
+    run += tmp[w];
   }
-  __syncthreads();
-  const double out = incl + tmp[wave];
-  total = tmp[NW];
-  __syncthreads();
+  const double out = incl + before;
+  total = run;
+  __syncthreads();  // tmp may be reused at once
   return out;
 }
 
@@ -186,15 +180,12 @@ __device__ __forceinline__ double block_sum_f64(double v, double* tmp) {
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
   if (lane == 0) tmp[wave] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double run = 0.0;
-    for (int w = 0; w < NW; ++w) run += tmp[w];
-    tmp[NW] = run;
-  }
-  __syncthreads();
-  const double r = tmp[NW];
-  __syncthreads();
-  return r;
+  // every thread adds the wavefront sums in the same order (same bits)
+  double run = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) run += tmp[w];
+  __syncthreads();  // tmp may be reused at once
+  return run;
 }
 
 template <int BLOCK>
@@ -206,15 +197,11 @@ __device__ __forceinline__ int block_sum_i32(int v, int* tmp) {
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
   if (lane == 0) tmp[wave] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int w = 0; w < NW; ++w) run += tmp[w];
-    tmp[NW] = run;
-  }
-  __syncthreads();
-  const int r = tmp[NW];
-  __syncthreads();
-  return r;
+  int run = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) run += tmp[w];
+  __syncthreads();  // tmp may be reused at once
+  return run;
 }
 
 // ---------------------------------------------------------------------------

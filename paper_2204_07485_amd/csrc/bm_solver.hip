@@ -1407,8 +1407,8 @@ __device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& 
   };
   if (a.sums_in_lds) rows(std::true_type{}, sums_l + static_cast<size_t>(rep_l) * rstride);
   else rows(std::false_type{}, ring);
-  __syncthreads();
   const uint64_t a2 = wall_clock64();
+  // the sum's barrier also completes every row's LDS accumulation before the flush
   const double wsse = block_sum_f64<kBlock>(sse, L.tmpd);
   const uint64_t f0 = wall_clock64();
   if (accumulate) {
