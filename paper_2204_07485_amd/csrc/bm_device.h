@@ -60,15 +60,18 @@ __device__ __forceinline__ bool grid_barrier(GridBarrier* b, unsigned int nblock
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = 1;
-    if (__hip_atomic_load(&b->abort.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    const unsigned int S = barrier_group_size(nblocks);
+    const unsigned int grp = blockIdx.x / S;
+    unsigned int* my_gen = &b->gen[grp].v;
+    // the abort flag and this group's generation are loaded together (one
+    // round trip); the generation cannot move before this workgroup arrives
+    const unsigned int aborted = __hip_atomic_load(&b->abort.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned int g = __hip_atomic_load(my_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (aborted) {
       ok = 0;
     } else {
-      const unsigned int S = barrier_group_size(nblocks);
-      const unsigned int grp = blockIdx.x / S;
       const unsigned int gsize = (nblocks - grp * S) < S ? (nblocks - grp * S) : S;
       const unsigned int ngroups = (nblocks + S - 1) / S;
-      unsigned int* my_gen = &b->gen[grp].v;
-      const unsigned int g = __hip_atomic_load(my_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       bool wait = true;
       const unsigned int prev =
