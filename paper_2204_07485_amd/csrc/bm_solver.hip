@@ -1455,10 +1455,15 @@ __device__ __forceinline__ double gather_pass(const SolverArgs& a, const LdsPlan
   const int kd = k * a.d;
   const int G = gridDim.x;
   const double* part = a.sse_part + (used & 1u) * kMaxGrid;
-  const int g0 = 2 * tid;
-  double v = 0.0;
-  if (g0 < G) v = part[g0];
-  if (g0 + 1 < G) v += part[g0 + 1];
+  // the objective: wavefront 0 adds the per-workgroup partials (lane l takes
+  // l, l + 64, ... in order, then a shuffle tree: a fixed order, so every
+  // workgroup gets the same bits); the first two per lane load with the sums
+  const int lane = tid & (kWave - 1);
+  double p0 = 0.0, p1 = 0.0;
+  if (tid < kWave) {
+    if (lane < G) p0 = part[lane];
+    if (lane + kWave < G) p1 = part[lane + kWave];
+  }
   const double* ring = a.sums + static_cast<size_t>(used % 3) * kReplicas * kd;
   const int32_t* cring = a.cnt + static_cast<size_t>(used % 3) * kReplicas * k;
   int* cnt_l = reinterpret_cast<int*>(L.B + pl.cntl);
@@ -1483,7 +1488,15 @@ __device__ __forceinline__ double gather_pass(const SolverArgs& a, const LdsPlan
     for (int q = 0; q < kReplicas; ++q) c += cring[static_cast<size_t>(q) * k + j];
     cnt_l[j] = c;
   }
-  return block_sum_f64<kBlock>(v, L.tmpd);
+  if (tid < kWave) {
+    double v = p0 + p1;
+    for (int g = lane + 2 * kWave; g < G; g += kWave) v += part[g];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+    if (tid == 0) L.miscd[2] = v;
+  }
+  __syncthreads();  // the staged sums, the counts and the objective
+  return L.miscd[2];
 }
 
 // New centroids from the gathered sums: the mean of each non-empty cluster as
@@ -1557,8 +1570,8 @@ __device__ __forceinline__ double update_centroids(const SolverArgs& a, const Ld
   }
   if (!need_shift) {
     __syncthreads();
+    // (the next pass reads the new centroids and slots after its own barrier)
     if (L.misc[3]) rebuild_active(L, k);  // a cluster emptied this round
-    __syncthreads();
     return 0.0;
   }
   // block max (exact, order-free)
