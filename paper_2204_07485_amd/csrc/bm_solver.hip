@@ -1408,8 +1408,16 @@ __device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& 
   if (a.sums_in_lds) rows(std::true_type{}, sums_l + static_cast<size_t>(rep_l) * rstride);
   else rows(std::false_type{}, ring);
   const uint64_t a2 = wall_clock64();
-  // the sum's barrier also completes every row's LDS accumulation before the flush
-  const double wsse = block_sum_f64<kBlock>(sse, L.tmpd);
+  // this workgroup's objective: wavefront sums, then thread 0 adds them in
+  // order (the barrier also completes every row's LDS accumulation before
+  // the flush; tmpd is next written after the grid barrier)
+  {
+    const int lane = tid & (kWave - 1);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) sse += __shfl_down(sse, o, kWave);
+    if (lane == 0) L.tmpd[tid / kWave] = sse;
+  }
+  __syncthreads();
   const uint64_t f0 = wall_clock64();
   if (accumulate) {
     auto count = [&](int j) {
@@ -1432,7 +1440,12 @@ __device__ __forceinline__ bool assign_pass(const SolverArgs& a, const LdsPlan& 
       if (c) atomicAdd(&cring[j], c);
     }
   }
-  if (tid == 0) a.sse_part[(pass & 1u) * kMaxGrid + g] = wsse;
+  if (tid == 0) {
+    double wsse = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) wsse += L.tmpd[w];
+    a.sse_part[(pass & 1u) * kMaxGrid + g] = wsse;
+  }
   const uint64_t b0 = wall_clock64();
   const bool ok = sync_grid(a);
   if (g == 0 && tid == 0) {
