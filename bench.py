@@ -400,8 +400,8 @@ def serve_stream(n_jobs=200, slots=4, rate=200.0, seed=5):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (asked for {args.gpus}); "
+              "multi-GPU sharding is not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
