@@ -49,7 +49,7 @@ enum {
   BM_EINVAL = -1,      /* invalid argument (sizes, null pointers, options) */
   BM_ENOMEM = -2,      /* device or host allocation failed                 */
   BM_EDEVICE = -3,     /* a HIP call or a kernel failed                    */
-  BM_ENOTSUP = -4,     /* a valid request this build cannot serve          */
+  BM_ENOTSUP = -4,     /* a valid request this library cannot serve        */
   BM_ECANCELLED = -5,  /* the work was cancelled                           */
   BM_ETIMEDOUT = -6    /* a wait ran out of time (the work goes on)        */
 };
